@@ -1,0 +1,142 @@
+/*
+ * librqrcp -- truncated randomized QR with column pivoting (RQRCP) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Xiao, Gu, Langou, "Fast Parallel Randomized QR with Column Pivoting
+ * Algorithms for Reliable Low-rank Matrix Approximations" (HiPC 2017,
+ * arXiv 1804.05138).  The factorization is A Pi = Q R (eq. (1)) truncated at
+ * target rank k:
+ *
+ *     A Pi = Q [R11 R12; 0 R22],   A ~ Q1 [R11 R12] Pi^T     (Section I-A)
+ *
+ * computed with Alg. 2 (RQRCP): a Gaussian sketch B = Omega A
+ * (Omega ~ N(0,1)^{(b+p) x m}), then per block of b columns a partial QRCP of
+ * the sketch (Alg. 1) picks b pivots, the pivoted panel of A is factored by
+ * Householder QR, the block reflector is applied to the trailing columns, and
+ * the sketch is refreshed with update formula (1) of Section III-B.
+ *
+ * Conventions (all entry points):
+ *  - Matrices are column-major with a leading dimension >= the row count.
+ *    Indices are 0-based.  Every array argument is DEVICE memory unless its
+ *    comment says (host).
+ *  - Work is enqueued on the handle's stream and is asynchronous, except
+ *    where a comment says the call synchronizes.  The caller owns every
+ *    buffer; the library allocates nothing per call (the workspace comes
+ *    from rqrcp_workspace_size).  A, B and the workspace must not alias.
+ *  - Return value: 0 on success; -i if argument i (1-based) is invalid, in
+ *    which case nothing was enqueued; RQRCP_ERR_* otherwise.  Numerical
+ *    conditions are reported through the device `info` word.
+ *  - One handle per stream; a handle is not thread-safe.
+ *
+ * Storage of a factorization (LAPACK convention): on exit A holds R in its
+ * upper trapezoid (rows 0..k-1), the Householder vectors v_j (v_j[j] = 1
+ * implied) below the diagonal of columns 0..k-1, and the trailing block R22
+ * in A(k:m, k:n).  tau[j] are the reflector scalars, H_j = I - tau_j v_j v_j^T,
+ * Q = H_0 H_1 ... H_{k-1}.  jpvt[j] is the original index of the column at
+ * position j.  The reflector convention is LAPACK dlarfg's:
+ * beta = -sign(alpha) ||x||, with sign(0) = +.
+ */
+#ifndef RQRCP_H
+#define RQRCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rqrcp_ctx *rqrcp_handle;
+
+/* Status codes (besides 0 and -i). */
+#define RQRCP_ERR_HIP 1001         /* a HIP runtime call or launch failed */
+#define RQRCP_ERR_WORKSPACE 1002   /* ws_bytes smaller than rqrcp_workspace_size */
+#define RQRCP_ERR_UNSUPPORTED 1003 /* dtype combination not supported */
+#define RQRCP_ERR_DEVICE 1004      /* the current device is not gfx950 */
+#define RQRCP_ERR_LIMIT 1005       /* size beyond what the kernels accept (see rqrcp_limits) */
+#define RQRCP_ERR_BARRIER 1006     /* a persistent kernel's grid barrier timed out */
+
+/* Element types. */
+#define RQRCP_F64 0
+#define RQRCP_F32 1
+
+/* rqrcp_params.flags */
+#define RQRCP_FROZEN_PIVOTS 1u /* jpvt is an input: factor A(:, jpvt) without pivoting */
+#define RQRCP_USER_SKETCH 2u   /* B already holds the sketch Omega A (e.g. from rqrcp_sketch) */
+
+typedef struct {
+  int b;          /* block size, 1 <= b <= 128 (Alg. 2 "block size b") */
+  int p;          /* oversampling, p >= 0, b + p <= 160 (Alg. 2 "oversampling size p") */
+  uint64_t seed;  /* Philox key word 0 of Omega (key word 1 = stream 0) */
+  int a_type;     /* RQRCP_F64 (only type of this version) */
+  unsigned flags; /* RQRCP_FROZEN_PIVOTS | RQRCP_USER_SKETCH */
+} rqrcp_params;
+
+/* Create a handle bound to `stream` (a hipStream_t; NULL = default stream)
+ * on the current device.  Fails with RQRCP_ERR_DEVICE if that device is not
+ * gfx950.  *h (host) receives the handle. */
+int rqrcp_create(rqrcp_handle *h, void *stream);
+int rqrcp_destroy(rqrcp_handle h);
+int rqrcp_set_stream(rqrcp_handle h, void *stream);
+
+/* Workspace in bytes (host output) for rqrcp_factor with these sizes.  A
+ * workspace of that size also serves rqrcp_sketch and rqrcp_form_q for the
+ * same m, n, k, b, p. */
+int rqrcp_workspace_size(int m, int n, int k, const rqrcp_params *prm, size_t *bytes);
+
+/* Largest sizes the kernels accept for sketch row count l = b + p (host
+ * outputs): max_b, max_l, and max_n (columns of the sketch QRCP). */
+int rqrcp_limits(int l, int *max_b, int *max_l, int *max_n);
+
+/* Omega(0:rows, 0:cols) ~ N(0,1) from the counter-based generator
+ * Philox4x64-10 (Salmon et al., SC'11) with key (seed, stream):
+ * entry (r, c) is normal number q = c*rows + r, taken from counter
+ * (q/4 + 1, 0, 0, 0), word q%4, uniform u = ((x >> 12) + 1/2) 2^-52 and
+ * Box-Muller on word pairs (0,1) and (2,3).  Alg. 2 draws the (b+p) x m
+ * sketching matrix from stream 0; Alg. 3 draws its probes from stream
+ * 2^32 + j.  out: rows x cols, leading dimension ld. */
+int rqrcp_gaussian(rqrcp_handle h, int rows, int cols, uint64_t seed, uint64_t stream,
+                   double *out, int ld);
+
+/* Sketch B = Omega A (Alg. 2, "Compute B = Omega A"); A is m x n FP64 (lda),
+ * B is l x n FP64 (ldb).  Omega: l x m FP64 (ldo) supplied by the caller, or
+ * NULL to draw it from Philox(seed, stream 0) into the workspace. */
+int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, const double *A, int lda,
+                 const double *Omega, int ldo, double *B, int ldb, void *ws, size_t ws_bytes);
+
+/* Truncated RQRCP (Alg. 2) of the m x n matrix A to rank k, 1 <= k <= min(m, n).
+ *  A     (in/out) m x n, lda: the factorization in LAPACK storage (see top).
+ *  jpvt  (out) n ints; with RQRCP_FROZEN_PIVOTS an input permutation.
+ *  tau   (out) k doubles.
+ *  B     (in/out) (b+p) x n sketch, ldb >= b+p.  Computed from Philox(seed)
+ *        unless RQRCP_USER_SKETCH; on exit B(:, k:n) is the sketch of the
+ *        trailing block R22 (the input of srqr).  Unused (may be NULL) with
+ *        RQRCP_FROZEN_PIVOTS.
+ *  info  (out, one int) 0, or s+1 if the largest trailing sketch norm at
+ *        global pivot step s was exactly zero (then the sketch is no longer
+ *        updated and the remaining steps take the columns in their current
+ *        order; the factorization itself is completed).
+ * Pivot ties go to the lowest current position. */
+int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, double *A, int lda,
+                 int32_t *jpvt, double *tau, double *B, int ldb, int32_t *info, void *ws,
+                 size_t ws_bytes);
+
+/* Explicit Q1 = H_0 ... H_{k-1} [I_k; 0] (m x k, ldq) from a factorization
+ * (A, lda, tau); b is the block size used to apply the reflectors. */
+int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, const double *A, int lda, const double *tau,
+                 double *Q, int ldq, void *ws, size_t ws_bytes);
+
+/* Synchronizes the handle's stream and returns RQRCP_ERR_BARRIER if a
+ * persistent kernel reported a barrier timeout since the last check (and
+ * clears the flag), RQRCP_ERR_HIP on a HIP error, else 0.  `ws` is the
+ * workspace the kernels ran with. */
+int rqrcp_check(rqrcp_handle h, void *ws);
+
+/* Human-readable text of a status code (static storage). */
+const char *rqrcp_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQRCP_H */

@@ -27,9 +27,13 @@ Readings of points the paper leaves open (each one is listed in the design doc):
 * argmax ties go to the lowest current column position.
 * The garbled index "B(1:b, i:j+b-1)" of Alg. 2 / Alg. 4 is read as B(1:b, i:i+b-1).
 * The last block has bb = k - i columns; Omega and B keep b + p rows throughout.
-* Exact rank deficiency: if the largest trailing sketch norm at global step s
-  is exactly 0, the current block is cut to the steps before s, the
-  factorization stops after that block, info = s + 1 and tau[s:] = 0.
+* Exact rank deficiency (R11 assumed invertible in Section III-C): if the
+  largest trailing sketch norm at global step s is exactly 0, info = s + 1;
+  from then on no column is moved (the remaining steps take the columns in
+  their current order) and the sketch is no longer updated (formula (1)
+  needs R11^{-1}), while the Householder factorization of A is completed.
+  On exactly zero trailing columns this is the same as stopping at step s:
+  their reflectors are the identity (tau = 0).
 
 Storage is LAPACK's: on exit ``a`` holds R in its upper trapezoid (rows 0..k-1),
 the Householder vectors v (unit leading entry implied) below the diagonal of
@@ -92,20 +96,23 @@ def partial_qrcp(w: np.ndarray, nsteps: int, trace: StepTrace | None = None):
     """``nsteps`` steps of Alg. 1 on the sketch block ``w`` (in place).
 
     Returns (pivots, rank_stop): pivots[t] is the position (within w) that was
-    swapped into position t; rank_stop is the step at which every trailing norm
-    was exactly zero (then fewer than ``nsteps`` pivots are returned), or None.
+    swapped into position t; rank_stop is the first step at which every
+    trailing norm was exactly zero (that step and the later ones then keep the
+    current column order), or None.
     """
     rows, ncols = w.shape
     pivots = []
+    rank_stop = None
     for t in range(nsteps):
         # r_s = ||w(t:rows, s)||, recomputed for every trailing column s >= t
         norms = np.sqrt(np.sum(w[t:, t:] ** 2, axis=0))
         j = t + int(np.argmax(norms))          # first maximum = lowest position
-        if trace is not None:
+        if norms[j - t] == 0.0:
+            if rank_stop is None:
+                rank_stop = t
+        elif trace is not None:
             sq = np.sort(norms ** 2)[::-1]
             trace.top2.append((sq[0], sq[1] if sq.size > 1 else 0.0))
-        if norms[j - t] == 0.0:
-            return pivots, t
         if j != t:
             w[:, [t, j]] = w[:, [j, t]]
         beta, tau, v = householder(w[t, t], w[t + 1:, t])
@@ -113,7 +120,7 @@ def partial_qrcp(w: np.ndarray, nsteps: int, trace: StepTrace | None = None):
         w[t + 1:, t] = 0.0
         apply_reflector(np.concatenate(([1.0], v)), tau, w[t:, t + 1:])
         pivots.append(j)
-    return pivots, None
+    return pivots, rank_stop
 
 
 def qrcp(a: np.ndarray, k: int, trace: StepTrace | None = None):
@@ -228,16 +235,14 @@ def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
     while i < k:
         bb = min(b, k - i)
         w = bsk[:, i:]                             # view: partial QRCP acts on B(:, i:n)
-        pivots, rank_stop = partial_qrcp(w, bb, trace)
-        for t, j in enumerate(pivots):             # same transpositions on A and Pi
-            if j != t:
-                a[:, [i + t, i + j]] = a[:, [i + j, i + t]]
-                jpvt[[i + t, i + j]] = jpvt[[i + j, i + t]]
-        if rank_stop is not None:
-            info = i + rank_stop + 1
-            bb = rank_stop
-        if bb == 0:
-            break
+        if info == 0:
+            pivots, rank_stop = partial_qrcp(w, bb, trace)
+            for t, j in enumerate(pivots):         # same transpositions on A and Pi
+                if j != t:
+                    a[:, [i + t, i + j]] = a[:, [i + j, i + t]]
+                    jpvt[[i + t, i + j]] = jpvt[[i + j, i + t]]
+            if rank_stop is not None:
+                info = i + rank_stop + 1
         if mode == "plain":
             for t in range(bb):
                 c = i + t
@@ -251,7 +256,7 @@ def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
             apply_block_reflector_t(v, compact_wy_t(v, tau[i:i + bb]), a[i:, i + bb:])
         else:
             raise ValueError(mode)
-        if i + bb < n:
+        if i + bb < n and info == 0:
             if update == "formula1":
                 r11 = np.triu(a[i:i + bb, i:i + bb])
                 r12 = a[i:i + bb, i + bb:]
@@ -262,10 +267,6 @@ def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
                 q1 = form_q(a[:, :s], tau[:s])                        # m x s
                 w[:, bb:] = b_orig[:, jpvt[s:]] - (om @ q1) @ a[:s, s:]
         i += bb
-        if rank_stop is not None:
-            break
-    if info:
-        tau[info - 1:] = 0.0
     return Factorization(a, tau, jpvt, bsk, info, om, trace)
 
 

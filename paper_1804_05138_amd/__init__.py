@@ -1,0 +1,264 @@
+"""Python binding of librqrcp: truncated randomized QR with column pivoting on MI355X.
+
+Thin ctypes marshalling over the C ABI declared in ``include/rqrcp.h``: torch
+tensors supply device memory and the current HIP stream; every step of the
+factorization runs in the library's HIP kernels.  Importing works without a
+GPU; calling anything that computes requires the built ``librqrcp.so`` and a
+gfx950 device, and raises otherwise (there is no fallback path).
+
+Matrices are column-major: an m x n matrix is a tensor of shape (m, n) with
+strides (1, ld), e.g. ``torch.empty(n, m).t()``.  ``colmajor(x)`` converts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librqrcp.so")
+
+F64 = 0
+F32 = 1
+FROZEN_PIVOTS = 1
+USER_SKETCH = 2
+
+STATUS = {
+    1001: "HIP runtime error", 1002: "workspace too small",
+    1003: "unsupported data type combination", 1004: "device is not gfx950",
+    1005: "size beyond the kernels' limits", 1006: "grid barrier timed out",
+}
+
+# Every symbol declared in include/rqrcp.h.
+EXPORTS = (
+    "rqrcp_create", "rqrcp_destroy", "rqrcp_set_stream", "rqrcp_workspace_size",
+    "rqrcp_limits", "rqrcp_gaussian", "rqrcp_sketch", "rqrcp_factor", "rqrcp_form_q",
+    "rqrcp_check", "rqrcp_status_string",
+)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_int), ("p", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("a_type", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librqrcp.so (no GPU needed).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"librqrcp.so not built ({path}); run paper_1804_05138_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, i, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "rqrcp_create": (i, [P(vp), vp]),
+        "rqrcp_destroy": (i, [vp]),
+        "rqrcp_set_stream": (i, [vp, vp]),
+        "rqrcp_workspace_size": (i, [i, i, i, P(Params), P(sz)]),
+        "rqrcp_limits": (i, [i, P(i), P(i), P(i)]),
+        "rqrcp_gaussian": (i, [vp, i, i, u64, u64, vp, i]),
+        "rqrcp_sketch": (i, [vp, i, i, i, u64, vp, i, vp, i, vp, i, vp, sz]),
+        "rqrcp_factor": (i, [vp, i, i, i, P(Params), vp, i, vp, vp, vp, i, vp, vp, sz]),
+        "rqrcp_form_q": (i, [vp, i, i, i, vp, i, vp, vp, i, vp, sz]),
+        "rqrcp_check": (i, [vp, vp]),
+        "rqrcp_status_string": (ctypes.c_char_p, [i]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = STATUS.get(status, "invalid argument %d" % -status if status < 0 else "error")
+        raise RuntimeError(f"{what}: librqrcp status {status} ({msg})")
+
+
+# ---------------------------------------------------------------------------
+# handles and tensors
+# ---------------------------------------------------------------------------
+
+_handles = {}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def handle():
+    """The library handle bound to the current device and its current stream."""
+    torch = _torch()
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("librqrcp needs a GPU (torch.cuda is not available)")
+    stream = torch.cuda.current_stream().cuda_stream
+    key = (torch.cuda.current_device(), stream)
+    h = _handles.get(key)
+    if h is None:
+        h = ctypes.c_void_p()
+        _check(lib.rqrcp_create(ctypes.byref(h), ctypes.c_void_p(stream)), "rqrcp_create")
+        _handles[key] = h
+    return h
+
+
+def colmajor(x, dtype=None):
+    """Column-major copy (strides (1, rows)) of a 2-D tensor, unless it already is one."""
+    torch = _torch()
+    if dtype is not None and x.dtype != dtype:
+        x = x.to(dtype)
+    if x.dim() != 2:
+        raise ValueError("expected a matrix")
+    if x.stride(0) == 1 and x.stride(1) >= max(1, x.shape[0]):
+        return x
+    return x.t().contiguous().t()
+
+
+def empty_colmajor(m, n, dtype, device):
+    torch = _torch()
+    return torch.empty((n, m), dtype=dtype, device=device).t()
+
+
+def _ld(x):
+    return max(1, x.stride(1)) if x.shape[1] > 1 else max(1, x.shape[0])
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else ctypes.c_void_p(0)
+
+
+def workspace_bytes(m, n, k, b, p, flags=0):
+    lib = load_library()
+    out = ctypes.c_size_t()
+    prm = Params(b, p, 0, F64, flags)
+    _check(lib.rqrcp_workspace_size(m, n, k, ctypes.byref(prm), ctypes.byref(out)),
+           "rqrcp_workspace_size")
+    return out.value
+
+
+def workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(1, nbytes), dtype=torch.uint8, device=device)
+
+
+def limits(l):
+    lib = load_library()
+    mb, ml, mn = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    lib.rqrcp_limits(l, ctypes.byref(mb), ctypes.byref(ml), ctypes.byref(mn))
+    return mb.value, ml.value, mn.value
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+
+def gaussian(rows, cols, seed, stream=0, device="cuda"):
+    """Omega (rows x cols) from Philox4x64-10 key (seed, stream)."""
+    torch = _torch()
+    h = handle()
+    out = empty_colmajor(rows, cols, torch.float64, device)
+    _check(load_library().rqrcp_gaussian(h, rows, cols, seed, stream, _ptr(out),
+                                          max(1, rows)), "rqrcp_gaussian")
+    return out
+
+
+def sketch(a, l, seed=0, omega=None, ws=None):
+    """B = Omega A (l x n) for a column-major FP64 A."""
+    torch = _torch()
+    a = colmajor(a, torch.float64)
+    m, n = a.shape
+    h = handle()
+    b = empty_colmajor(l, n, torch.float64, a.device)
+    if omega is not None:
+        omega = colmajor(omega, torch.float64)
+    nbytes = workspace_bytes(m, n, 1, l, 0)
+    ws = workspace(nbytes, a.device) if ws is None else ws
+    _check(load_library().rqrcp_sketch(h, m, n, l, seed, _ptr(a), _ld(a), _ptr(omega),
+                                        _ld(omega) if omega is not None else 0, _ptr(b), l,
+                                        _ptr(ws), ws.numel()), "rqrcp_sketch")
+    return b
+
+
+@dataclass
+class Factorization:
+    a: object       # m x n column-major: R, V, R22 (LAPACK storage)
+    jpvt: object    # int32 (n,)
+    tau: object     # float64 (k,)
+    b: object       # sketch ((b+p) x n) or None
+    info: object    # int32 (1,)
+    k: int
+    block: int
+
+
+def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=False,
+           check=True):
+    """Truncated RQRCP (Alg. 2) of the FP64 matrix ``a`` to rank ``k``.
+
+    jpvt: frozen pivots (the columns A(:, jpvt) are factored without pivoting).
+    sketch_b: a precomputed sketch Omega A ((b+p) x n), e.g. with a custom Omega.
+    Returns a Factorization with device tensors.
+    """
+    torch = _torch()
+    if inplace:
+        if a.dtype != torch.float64 or a.stride(0) != 1:
+            raise ValueError("inplace needs a column-major float64 tensor")
+        af = a
+    else:
+        af = colmajor(a, torch.float64).clone(memory_format=torch.preserve_format)
+        if af.stride(0) != 1:
+            af = colmajor(af)
+    m, n = af.shape
+    dev = af.device
+    flags = 0
+    jp = torch.empty(n, dtype=torch.int32, device=dev)
+    if jpvt is not None:
+        flags |= FROZEN_PIVOTS
+        jp.copy_(torch.as_tensor(jpvt, dtype=torch.int32, device=dev))
+        bs = None
+    elif sketch_b is not None:
+        flags |= USER_SKETCH
+        bs = colmajor(sketch_b, torch.float64).clone()
+        if bs.stride(0) != 1:
+            bs = colmajor(bs)
+    else:
+        bs = empty_colmajor(b + p, n, torch.float64, dev)
+    tau = torch.empty(k, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = workspace_bytes(m, n, k, b, p, flags)
+    if ws is None or ws.numel() < nbytes:
+        ws = workspace(nbytes, dev)
+    prm = Params(b, p, seed, F64, flags)
+    lib = load_library()
+    h = handle()
+    _check(lib.rqrcp_factor(h, m, n, k, ctypes.byref(prm), _ptr(af), _ld(af), _ptr(jp),
+                            _ptr(tau), _ptr(bs), (_ld(bs) if bs is not None else b + p),
+                            _ptr(info), _ptr(ws), ws.numel()), "rqrcp_factor")
+    if check:
+        _check(lib.rqrcp_check(h, _ptr(ws)), "rqrcp_check")
+    return Factorization(af, jp, tau, bs, info, k, b)
+
+
+def form_q(fact_a, tau, k=None, b=64, ws=None):
+    """Explicit Q1 (m x k) of a factorization in LAPACK storage."""
+    torch = _torch()
+    k = tau.numel() if k is None else k
+    m = fact_a.shape[0]
+    q = empty_colmajor(m, k, torch.float64, fact_a.device)
+    nbytes = workspace_bytes(m, k, k, b, 0)
+    ws = workspace(nbytes, fact_a.device) if ws is None or ws.numel() < nbytes else ws
+    _check(load_library().rqrcp_form_q(handle(), m, k, b, _ptr(fact_a), _ld(fact_a), _ptr(tau),
+                                        _ptr(q), max(1, m), _ptr(ws), ws.numel()),
+           "rqrcp_form_q")
+    return q
+
+
+def check(ws=None):
+    _check(load_library().rqrcp_check(handle(), _ptr(ws)), "rqrcp_check")

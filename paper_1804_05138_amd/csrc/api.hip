@@ -1,0 +1,383 @@
+// C ABI of librqrcp: argument checks, workspace layout and the block loop of
+// Alg. 2 (RQRCP), reorganized so that each block needs one pass over the
+// trailing matrix:
+//
+//   B = Omega A;  QRCP(B) -> pivots of block 0;  move columns;  panel 0;
+//   W_0 = V_0^T A2 (one read of A2)
+//   for each block i:
+//     W'_i = T_i^T W_i;  R12;  sample update of B (formula (1))
+//     if another block follows:
+//        QRCP(B) -> its pivots; move columns of A, jpvt and W'_i
+//        panel i+1 (after applying block i's update to its own columns)
+//        fused pass: A2 -= V_i W'_i  and  W_{i+1} = V_{i+1}^T A2
+//     else: last pass A2 -= V_i W'_i
+//
+// The arithmetic is that of Alg. 2; only the order of independent work
+// changes: the next block's pivots depend on the sketch, which needs only W_i
+// (through R12), not on the rest of the trailing update.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/rqrcp.h"
+#include "gemm.h"
+#include "internal.h"
+
+struct rqrcp_ctx {
+  hipStream_t stream;
+  int device;
+};
+
+namespace {
+
+using namespace rq;
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t omega, sketch_part, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy, formq, total;
+};
+
+// Every workspace starts with the scratch words of the persistent kernels, so
+// that rqrcp_check can find their error flags without the call's sizes.
+constexpr size_t QSCR_OFF = 0;
+const size_t PSCR_OFF = (sizeof(rq::QrcpScratch) + 255) / 256 * 256;
+const size_t HEADER = PSCR_OFF + (sizeof(rq::PanelScratch) + 255) / 256 * 256;
+
+size_t wpart_doubles(int m, int n, int k, int b) {
+  size_t best = 0;
+  int i = 0;
+  int bb = std::min(b, k);
+  // W-only pass of block 0
+  {
+    const int nc = n - bb;
+    if (nc > 0) {
+      TrailPlan p = trail_plan(m, nc);
+      best = std::max(best, (size_t)p.nsplit * nc * bb);
+    }
+  }
+  while (i + bb < k) {
+    const int bbn = std::min(b, k - i - bb);
+    const int nc = n - (i + bb + bbn);
+    if (nc > 0) {
+      TrailPlan p = trail_plan(m - i, nc);
+      best = std::max(best, (size_t)p.nsplit * nc * bbn);
+    }
+    i += bb;
+    bb = bbn;
+  }
+  return best;
+}
+
+Layout layout(int m, int n, int k, int b, int p, unsigned flags) {
+  Layout L;
+  const int l = b + p;
+  size_t off = HEADER;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.omega = take((size_t)l * m * sizeof(double));
+  L.sketch_part = take(sketch_partial_doubles(m, n, l) * sizeof(double));
+  L.qscr = QSCR_OFF;
+  L.cand = take(qrcp_cand_doubles(l, n) * sizeof(double));
+  L.pairs = take(4 * MAX_B * sizeof(int));
+  L.pscr = PSCR_OFF;
+  L.ppart = take(panel_partial_doubles(m, std::min(b, k)) * sizeof(double));
+  L.tmat = take((size_t)MAX_B * MAX_B * sizeof(double));
+  L.wpart = take(wpart_doubles(m, n, k, b) * sizeof(double));
+  L.wp = take((size_t)b * n * sizeof(double));
+  L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * sizeof(double) : 0);
+  L.formq = take(form_q_work_elems(m, k, b) * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+__global__ void k_init(QrcpScratch* q, PanelScratch* p, int* info, int* jpvt, int n, int iota) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    q->bar.count = 0;
+    q->bar.err = 0;
+    q->npairs = 0;
+    p->bar.count = 0;
+    p->bar.err = 0;
+    *info = 0;
+  }
+  if (iota)
+    for (int j = t; j < n; j += gridDim.x * blockDim.x) jpvt[j] = j;
+}
+
+__global__ void k_copy_cols(int m, int n, const double* __restrict__ src, long long lds,
+                            double* __restrict__ dst, long long ldd, const int* __restrict__ perm) {
+  const long long total = (long long)m * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long c = e / m, r = e % m;
+    const long long sc = perm ? perm[c] : c;
+    dst[c * ldd + r] = src[sc * lds + r];
+  }
+}
+
+unsigned grid_for(long long total) {
+  long long g = (total + 255) / 256;
+  return (unsigned)std::max<long long>(1, std::min<long long>(g, 65536));
+}
+
+bool valid_params(const rqrcp_params* prm) {
+  return prm && prm->b >= 1 && prm->p >= 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rqrcp_create(rqrcp_handle* h, void* stream) {
+  if (!h) return -1;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RQRCP_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return RQRCP_ERR_HIP;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RQRCP_ERR_DEVICE;
+  rqrcp_ctx* c = new (std::nothrow) rqrcp_ctx;
+  if (!c) return RQRCP_ERR_HIP;
+  c->stream = (hipStream_t)stream;
+  c->device = dev;
+  *h = c;
+  return 0;
+}
+
+int rqrcp_destroy(rqrcp_handle h) {
+  if (!h) return -1;
+  delete h;
+  return 0;
+}
+
+int rqrcp_set_stream(rqrcp_handle h, void* stream) {
+  if (!h) return -1;
+  h->stream = (hipStream_t)stream;
+  return 0;
+}
+
+int rqrcp_limits(int l, int* max_b, int* max_l, int* max_n) {
+  if (max_b) *max_b = MAX_B;
+  if (max_l) *max_l = MAX_L;
+  // one sketch column per thread (two for l > 48), one 256-thread workgroup per compute unit
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (max_n) *max_n = (l <= 48 ? 256 : 128) * ncu;
+  return 0;
+}
+
+int rqrcp_workspace_size(int m, int n, int k, const rqrcp_params* prm, size_t* bytes) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (k < 1 || k > std::min(m, n)) return -3;
+  if (!valid_params(prm)) return -4;
+  if (!bytes) return -5;
+  *bytes = layout(m, n, k, prm->b, prm->p, prm->flags).total;
+  return 0;
+}
+
+int rqrcp_gaussian(rqrcp_handle h, int rows, int cols, uint64_t seed, uint64_t stream, double* out,
+                   int ld) {
+  if (!h) return -1;
+  if (rows < 0) return -2;
+  if (cols < 0) return -3;
+  if (!out && rows * (long long)cols > 0) return -6;
+  if (ld < std::max(1, rows)) return -7;
+  return launch_gaussian(h->stream, rows, cols, seed, stream, out, ld);
+}
+
+int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, const double* A, int lda,
+                 const double* Omega, int ldo, double* B, int ldb, void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (l < 1 || l > MAX_L) return -4;
+  if (!A) return -6;
+  if (lda < m) return -7;
+  if (Omega && ldo < l) return -9;
+  if (!B) return -10;
+  if (ldb < l) return -11;
+  const size_t need = HEADER + align_up((size_t)l * m * sizeof(double)) +
+                      align_up(sketch_partial_doubles(m, n, l) * sizeof(double));
+  if (!ws || ws_bytes < need) return RQRCP_ERR_WORKSPACE;
+  char* w = (char*)ws + HEADER;
+  double* om = (double*)w;
+  double* part = (double*)(w + align_up((size_t)l * m * sizeof(double)));
+  long long ldo_eff = ldo;
+  if (!Omega) {
+    int rc = launch_gaussian(h->stream, l, m, seed, 0, om, l);
+    if (rc) return rc;
+    Omega = om;
+    ldo_eff = l;
+  }
+  return launch_sketch_f64(h->stream, m, n, l, Omega, ldo_eff, A, lda, B, ldb, part);
+}
+
+int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, double* A, int lda,
+                 int32_t* jpvt, double* tau, double* B, int ldb, int32_t* info, void* ws,
+                 size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  if (!valid_params(prm)) return -5;
+  const int b = prm->b, p = prm->p, l = b + p;
+  const bool frozen = (prm->flags & RQRCP_FROZEN_PIVOTS) != 0;
+  if (b > MAX_B || l > MAX_L) return RQRCP_ERR_LIMIT;
+  if (prm->a_type != RQRCP_F64) return RQRCP_ERR_UNSUPPORTED;
+  if (!A) return -6;
+  if (lda < m) return -7;
+  if (!jpvt) return -8;
+  if (!tau) return -9;
+  if (!frozen && !B) return -10;
+  if (!frozen && ldb < l) return -11;
+  if (!info) return -12;
+  const Layout L = layout(m, n, k, b, p, prm->flags);
+  if (!ws || ws_bytes < L.total) return RQRCP_ERR_WORKSPACE;
+  if (!frozen) {
+    int maxn = 0;
+    rqrcp_limits(l, nullptr, nullptr, &maxn);
+    if (n > maxn) return RQRCP_ERR_LIMIT;
+  }
+
+  hipStream_t s = h->stream;
+  char* w = (char*)ws;
+  double* om = (double*)(w + L.omega);
+  double* spart = (double*)(w + L.sketch_part);
+  QrcpScratch* qscr = (QrcpScratch*)(w + L.qscr);
+  double* cand = (double*)(w + L.cand);
+  int* pairs = (int*)(w + L.pairs);
+  PanelScratch* pscr = (PanelScratch*)(w + L.pscr);
+  double* ppart = (double*)(w + L.ppart);
+  double* tmat = (double*)(w + L.tmat);
+  double* wpart = (double*)(w + L.wpart);
+  double* wp = (double*)(w + L.wp);
+  const long long ldw = b;
+  int rc;
+
+  hipLaunchKernelGGL(k_init, dim3(grid_for(n)), dim3(256), 0, s, qscr, pscr, info, jpvt, n,
+                     frozen ? 0 : 1);
+  RQ_HIP_CHECK(hipGetLastError());
+
+  if (frozen) {
+    double* cp = (double*)(w + L.copy);
+    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n,
+                       (const double*)A, (long long)lda, cp, (long long)m, (const int*)nullptr);
+    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n,
+                       (const double*)cp, (long long)m, A, (long long)lda, (const int*)jpvt);
+    RQ_HIP_CHECK(hipGetLastError());
+  } else if (!(prm->flags & RQRCP_USER_SKETCH)) {
+    rc = launch_gaussian(s, l, m, prm->seed, 0, om, l);
+    if (rc) return rc;
+    rc = launch_sketch_f64(s, m, n, l, om, l, A, lda, B, ldb, spart);
+    if (rc) return rc;
+  }
+
+  int i = 0;
+  int bb = std::min(b, k);
+  int nsp = 0;
+  if (!frozen) {
+    rc = launch_qrcp_sketch(s, B, ldb, l, 0, n, bb, 0, qscr, cand, pairs, info);
+    if (rc) return rc;
+    rc = launch_apply_pairs(s, m, A, lda, 0, jpvt, nullptr, 0, 0, 0, pairs, &qscr->npairs,
+                            2 * bb, nullptr);
+    if (rc) return rc;
+  }
+  rc = launch_panel(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart);
+  if (rc) return rc;
+  {
+    TrailPlan pl = trail_plan(m, n - bb);
+    rc = launch_trail_f64(s, m, A, lda, 0, 0, bb, nullptr, 0, 0, bb, n, wpart, pl.nsplit, &nsp);
+    if (rc) return rc;
+  }
+  for (;;) {
+    const int c0 = i + bb;
+    const int ncols = n - c0;
+    rc = launch_bupdate(s, m, A, lda, i, bb, tmat, wpart, nsp, wp, ldw, frozen ? nullptr : B, ldb,
+                        c0, ncols, info);
+    if (rc) return rc;
+    if (c0 < k) {
+      const int bbn = std::min(b, k - c0);
+      if (!frozen) {
+        rc = launch_qrcp_sketch(s, B, ldb, l, c0, ncols, bbn, c0, qscr, cand, pairs, info);
+        if (rc) return rc;
+        rc = launch_apply_pairs(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs, &qscr->npairs,
+                                2 * bbn, nullptr);
+        if (rc) return rc;
+      }
+      rc = launch_panel(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart);
+      if (rc) return rc;
+      TrailPlan pl = trail_plan(m - i, n - (c0 + bbn));
+      rc = launch_trail_f64(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw, c0 + bbn,
+                            c0 + bbn, n, wpart, pl.nsplit, &nsp);
+      if (rc) return rc;
+      i = c0;
+      bb = bbn;
+    } else {
+      int dummy = 0;
+      rc = launch_trail_f64(s, m, A, lda, i, bb, 0, wp, ldw, c0, c0, n, nullptr, 1, &dummy);
+      if (rc) return rc;
+      break;
+    }
+  }
+  return 0;
+}
+
+int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, const double* A, int lda, const double* tau,
+                 double* Q, int ldq, void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (k < 1 || k > m) return -3;
+  if (b < 1 || b > MAX_B) return -4;
+  if (!A) return -5;
+  if (lda < m) return -6;
+  if (!tau) return -7;
+  if (!Q) return -8;
+  if (ldq < m) return -9;
+  if (!ws || ws_bytes < HEADER + form_q_work_elems(m, k, b) * sizeof(double))
+    return RQRCP_ERR_WORKSPACE;
+  return launch_form_q(h->stream, m, k, b, A, lda, tau, Q, ldq, (double*)((char*)ws + HEADER));
+}
+
+int rqrcp_check(rqrcp_handle h, void* ws) {
+  if (!h) return -1;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return RQRCP_ERR_HIP;
+  if (hipGetLastError() != hipSuccess) return RQRCP_ERR_HIP;
+  if (!ws) return 0;
+  char* w = (char*)ws;
+  GridBarrier bars[2];
+  if (hipMemcpy(&bars[0], w + QSCR_OFF, sizeof(GridBarrier), hipMemcpyDeviceToHost) != hipSuccess)
+    return RQRCP_ERR_HIP;
+  if (hipMemcpy(&bars[1], w + PSCR_OFF, sizeof(GridBarrier), hipMemcpyDeviceToHost) != hipSuccess)
+    return RQRCP_ERR_HIP;
+  if (bars[0].err || bars[1].err) {
+    const unsigned zero[3] = {0, 0, 0};
+    hipMemcpy(w + QSCR_OFF, zero, sizeof(zero), hipMemcpyHostToDevice);
+    hipMemcpy(w + PSCR_OFF, zero, sizeof(zero), hipMemcpyHostToDevice);
+    return RQRCP_ERR_BARRIER;
+  }
+  return 0;
+}
+
+const char* rqrcp_status_string(int status) {
+  if (status == 0) return "success";
+  if (status < 0) return "invalid argument";
+  switch (status) {
+    case RQRCP_ERR_HIP: return "HIP runtime error";
+    case RQRCP_ERR_WORKSPACE: return "workspace too small";
+    case RQRCP_ERR_UNSUPPORTED: return "unsupported data type combination";
+    case RQRCP_ERR_DEVICE: return "device is not gfx950";
+    case RQRCP_ERR_LIMIT: return "size beyond the kernels' limits";
+    case RQRCP_ERR_BARRIER: return "grid barrier timed out";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

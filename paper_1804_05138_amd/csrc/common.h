@@ -1,0 +1,195 @@
+// Shared device helpers for librqrcp (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RQ_DEV __device__ __forceinline__
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Status codes (mirrored in include/rqrcp.h)
+// ---------------------------------------------------------------------------
+enum {
+  RQ_OK = 0,
+  RQ_ERR_HIP = 1001,
+  RQ_ERR_WORKSPACE = 1002,
+  RQ_ERR_UNSUPPORTED = 1003,
+  RQ_ERR_DEVICE = 1004,
+  RQ_ERR_LIMIT = 1005,
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11) and Box-Muller normals.
+// key = (seed, stream); normal number q uses counter (q/4 + 1, 0, 0, 0) and
+// output word q%4; u = ((x >> 12) + 1/2) 2^-52.
+// ---------------------------------------------------------------------------
+namespace rq {
+
+constexpr uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t PHILOX_M1 = 0xCA5A826395121157ull;
+constexpr uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t PHILOX_W1 = 0xBB67AE8584CAA73Bull;
+constexpr double TWO_PI = 6.283185307179586;
+
+RQ_DEV void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(PHILOX_M0, c[0]);
+    const uint64_t lo0 = PHILOX_M0 * c[0];
+    const uint64_t hi1 = __umul64hi(PHILOX_M1, c[2]);
+    const uint64_t lo1 = PHILOX_M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0;
+    const uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += PHILOX_W0;
+    k1 += PHILOX_W1;
+  }
+}
+
+RQ_DEV double philox_uniform(uint64_t x) {
+  return ((double)(x >> 12) + 0.5) * 0x1p-52;
+}
+
+// The four normals of counter block `blk` (= q/4) of stream (seed, stream).
+RQ_DEV void philox_normals4(uint64_t blk, uint64_t seed, uint64_t stream, double z[4]) {
+  uint64_t c[4] = {blk + 1, 0, 0, 0};
+  philox4x64_10(c, seed, stream);
+  const double u0 = philox_uniform(c[0]), u1 = philox_uniform(c[1]);
+  const double u2 = philox_uniform(c[2]), u3 = philox_uniform(c[3]);
+  const double r01 = sqrt(-2.0 * log(u0));
+  const double r23 = sqrt(-2.0 * log(u2));
+  const double t01 = TWO_PI * u1;
+  const double t23 = TWO_PI * u3;
+  z[0] = r01 * cos(t01);
+  z[1] = r01 * sin(t01);
+  z[2] = r23 * cos(t23);
+  z[3] = r23 * sin(t23);
+}
+
+// ---------------------------------------------------------------------------
+// MFMA wrappers.  Operand layouts of the 16x16x4 forms (64 lanes):
+//   A (16x4):  lane l holds A[l % 16][l / 16]
+//   B (4x16):  lane l holds B[l / 16][l % 16]
+//   C/D (16x16), FP64: lane l, element e holds D[l / 16 + 4 e][l % 16]
+//   C/D (16x16), FP32: lane l, element e holds D[4 (l / 16) + e][l % 16]
+// acc_row<T>(g, e) gives the row for g = l / 16.
+// ---------------------------------------------------------------------------
+RQ_DEV v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+RQ_DEV v4f mfma_f32(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T>
+RQ_DEV int acc_row(int g, int e);
+template <>
+RQ_DEV int acc_row<double>(int g, int e) { return g + 4 * e; }
+template <>
+RQ_DEV int acc_row<float>(int g, int e) { return 4 * g + e; }
+
+// ---------------------------------------------------------------------------
+// Grid-wide barrier for persistent (co-resident) grids.  Sense-reversing:
+// the last arriving workgroup resets the counter and bumps the generation,
+// so the state is reusable across barriers and launches.  Every wait is
+// bounded: after `RQ_SPIN_LIMIT` polls the waiter raises *err and proceeds,
+// so a grid that is not fully resident still terminates.
+// ---------------------------------------------------------------------------
+struct GridBarrier {
+  unsigned count;
+  unsigned gen;
+  unsigned err;
+  unsigned pad[61];  // keep the flag lines apart from other data
+};
+
+#ifndef RQ_SPIN_LIMIT
+#define RQ_SPIN_LIMIT (1u << 24)
+#endif
+
+RQ_DEV unsigned atomic_load_agent(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-workgroup barrier state kept in LDS.
+struct BarrierLocal {
+  unsigned g0;
+  unsigned last;
+};
+
+// Phase 1 (all threads): arrive.  Returns true in every thread of the last
+// workgroup to arrive; that workgroup then sees every other workgroup's
+// global writes made before their arrival.
+RQ_DEV bool grid_arrive(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned g0 = atomic_load_agent(&bar->gen);
+    __threadfence();
+    const unsigned arrived = atomicAdd(&bar->count, 1u);
+    bl->g0 = g0;
+    bl->last = (arrived == nwg - 1) ? 1u : 0u;
+    __threadfence();
+  }
+  __syncthreads();
+  return bl->last != 0;
+}
+
+// Phase 2a (all threads of the last workgroup): release the others.
+RQ_DEV void grid_release(GridBarrier* bar) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+}
+
+// Phase 2b (all threads of the other workgroups): bounded wait.
+RQ_DEV void grid_wait(GridBarrier* bar, const BarrierLocal* bl) {
+  if (threadIdx.x == 0) {
+    unsigned spins = 0;
+    while (atomic_load_agent(&bar->gen) == bl->g0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > RQ_SPIN_LIMIT) {
+        atomicOr(&bar->err, 1u);
+        break;
+      }
+      if ((spins & 1023u) == 0 && atomic_load_agent(&bar->err)) break;
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+RQ_DEV void grid_barrier(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {
+  if (grid_arrive(bar, nwg, bl))
+    grid_release(bar);
+  else
+    grid_wait(bar, bl);
+}
+
+// ---------------------------------------------------------------------------
+// Misc.
+// ---------------------------------------------------------------------------
+RQ_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T>
+RQ_DEV T ld_elem(const T* p) { return *p; }
+
+}  // namespace rq
+
+// Host-side helper
+#define RQ_HIP_CHECK(expr)                                   \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return RQ_ERR_HIP;                 \
+  } while (0)

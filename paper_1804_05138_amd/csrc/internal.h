@@ -1,0 +1,87 @@
+// Host-side launchers shared between the kernel translation units and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace rq {
+
+// Scratch of the persistent sketch-QRCP kernel (lives in the workspace).
+struct QrcpScratch {
+  GridBarrier bar;
+  int npairs;
+  int pad[63];
+};
+
+// Scratch of the persistent panel kernel.
+struct PanelScratch {
+  GridBarrier bar;
+};
+
+constexpr int MAX_B = 128;      // largest block size b the kernels accept
+constexpr int MAX_L = 160;      // largest b + p the kernels accept
+
+// Omega (rows x cols, column-major, leading dimension ld) from Philox(seed, stream).
+int launch_gaussian(hipStream_t s, int rows, int cols, uint64_t seed, uint64_t stream,
+                    double* out, long long ld);
+
+// B(0:l, 0:n) = Omega(0:l, 0:m) * A(0:m, 0:n), all FP64 column-major.
+// `partial` holds split-K partial products (size partial_size_f64(...) doubles).
+size_t sketch_partial_doubles(int m, int n, int l);
+int launch_sketch_f64(hipStream_t s, int m, int n, int l, const double* om, long long ldo,
+                      const double* a, long long lda, double* b, long long ldb, double* partial);
+
+// Partial QRCP (Alg. 1) on the l x nc block of B starting at column c0.
+// On exit B holds the transformed block with its columns in pivot order;
+// `pairs` (2 ints per entry: destination position, source position, both
+// relative to c0) lists every column that moved, `scr->npairs` their count.
+int qrcp_sketch_grid(int l, int nc);
+int launch_qrcp_sketch(hipStream_t s, double* b, long long ldb, int l, int c0, int nc,
+                       int nsteps, int gstep0, QrcpScratch* scr, double* cand, int* pairs,
+                       int* info);
+size_t qrcp_cand_doubles(int l, int nc);
+
+// Column moves from `pairs` (count at *npairs) applied to A(0:m, c0 + .),
+// jpvt(c0 + .) and W'(0:wrows, w0 + .) (W' may be null).
+int launch_apply_pairs(hipStream_t s, int m, double* a, long long lda, int c0, int* jpvt,
+                       double* wp, int wrows, long long ldw, int w0, const int* pairs,
+                       const int* npairs, int max_pairs, double* tmp);
+
+// Panel QR of A(i:m, i:i+bb) with the previous block's pending update
+// A(ip:m, i:i+bb) -= Vprev * Wp(:, 0:bb) applied first (if bbp > 0, ip = i - bbp).
+// Writes V/R in place, tau(i:i+bb) and T (bb x bb, column-major, ld bb).
+int panel_grid(int rows, int bb);
+int launch_panel(hipStream_t s, int m, double* a, long long lda, int i, int bb, int bbp,
+                 const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
+                 double* partial);
+size_t panel_partial_doubles(int rows, int bb);
+
+// Trailing pass over columns [c_begin, c_end) of A, rows [i, m):
+//   if bbu > 0:  A(i:m, c) -= V_i * Wp(:, c - w0)      (V_i = A(i:m, i:i+bbu) reflectors)
+//   if bbn > 0:  Wpart(s, :, c - c_begin) = V_n^T A(in:m, c) (V_n = A(in:m, in:in+bbn),
+//                in = i + bbu), summed over row splits s by the consumer.
+struct TrailPlan {
+  int nsplit;
+  int ntiles;
+};
+TrailPlan trail_plan(int m_rows, int ncols);
+int launch_trail_f64(hipStream_t s, int m, double* a, long long lda, int i, int bbu, int bbn,
+                     const double* wp, long long ldw, int w0, int c_begin, int c_end,
+                     double* wpart, int nsplit, int* nsp_out);
+
+// From the split partials of W = V^T A2 (bb x ncols): W' = T^T W (stored at wp),
+// then R12 = A(i:i+bb, c) - V11 W'(:, c), X = R11^-1 R12 and
+// B(0:bb, c) -= Rhat11 X for the columns c = c0 .. c0 + ncols - 1 (skipped when
+// *info != 0).  Rhat11 = triu(B(0:bb, i:i+bb)).
+int launch_bupdate(hipStream_t s, int m, const double* a, long long lda, int i, int bb,
+                   const double* t, const double* wpart, int nsplit, double* wp, long long ldw,
+                   double* bsk, long long ldb, int c0, int ncols, const int* info);
+
+// Explicit Q1 = H_0 ... H_{k-1} [I; 0] (m x k) from LAPACK storage.
+int launch_form_q(hipStream_t s, int m, int k, int b, const double* a, long long lda,
+                  const double* tau, double* q, long long ldq, double* work);
+
+}  // namespace rq

@@ -1,0 +1,91 @@
+// Sample update of Alg. 2 with updating formula (1) of Section III-B:
+//     B(0:b, c) <- B(0:b, c) - Rhat11 R11^{-1} R12(:, c)
+// for every trailing column c, where Rhat11 = triu(B(0:b, i:i+b)) is the top
+// of the QRCP-transformed sketch and R11, R12 are the new rows of R.
+//
+// The kernel also finishes the block-reflector factor for the trailing pass:
+// from the split partial sums of W = V^T A2 it forms W' = T^T W (stored for
+// the next pass and the next panel), and R12 = A2(0:b, c) - V11 W'(:, c) is
+// obtained from W' directly (V11 = unit lower top block of V), so the sample
+// update does not wait for the trailing pass.
+//
+// One workgroup per 64 columns; lane = column, the four waves split the rows
+// of every triangular product; the triangular solve runs in wave 0.
+#include "internal.h"
+
+namespace rq {
+namespace {
+
+constexpr int BT = 256;
+
+__global__ __launch_bounds__(BT) void k_bupdate(int m, const double* __restrict__ a, long long lda,
+                                                int i, int bb, const double* __restrict__ tm,
+                                                const double* __restrict__ wpart, int nsplit,
+                                                double* __restrict__ wp, long long ldw,
+                                                double* __restrict__ bsk, long long ldb, int c0,
+                                                int ncols, const int* __restrict__ info) {
+  __shared__ double v0[MAX_B * 64];
+  __shared__ double v1[MAX_B * 64];
+  const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int cl = blockIdx.x * 64 + lane;  // column index relative to c0
+  const bool ok = cl < ncols;
+  const int col = c0 + cl;
+
+  // W(:, c) = sum of the split partials
+  for (int q = part; q < bb; q += 4) {
+    double s = 0.0;
+    if (ok)
+      for (int sp = 0; sp < nsplit; ++sp) s += wpart[((long long)sp * ncols + cl) * bb + q];
+    v0[q * 64 + lane] = s;
+  }
+  __syncthreads();
+  // W' = T^T W   (T upper triangular, column-major bb x bb)
+  for (int r = part; r < bb; r += 4) {
+    double s = 0.0;
+    for (int q = 0; q <= r; ++q) s += tm[r * bb + q] * v0[q * 64 + lane];
+    v1[r * 64 + lane] = s;
+    if (ok) wp[(long long)cl * ldw + r] = s;
+  }
+  __syncthreads();
+  // no sketch (frozen pivots), or no more sketch updates after a zero pivot
+  if (bsk == nullptr || *info != 0) return;
+  // R12 = A(i:i+bb, col) - V11 W'
+  for (int r = part; r < bb; r += 4) {
+    double s = ok ? a[(long long)col * lda + i + r] - v1[r * 64 + lane] : 0.0;
+    for (int q = 0; q < r; ++q) s -= a[(long long)(i + q) * lda + i + r] * v1[q * 64 + lane];
+    v0[r * 64 + lane] = s;
+  }
+  __syncthreads();
+  // X = R11^{-1} R12 (back substitution), into v1
+  if (part == 0) {
+    for (int r = bb - 1; r >= 0; --r) {
+      double s = v0[r * 64 + lane];
+      for (int q = r + 1; q < bb; ++q) s -= a[(long long)(i + q) * lda + i + r] * v1[q * 64 + lane];
+      v1[r * 64 + lane] = s / a[(long long)(i + r) * lda + i + r];
+    }
+  }
+  __syncthreads();
+  // B(0:bb, col) -= Rhat11 X
+  if (ok) {
+    for (int r = part; r < bb; r += 4) {
+      double s = 0.0;
+      for (int q = r; q < bb; ++q) s += bsk[(long long)(i + q) * ldb + r] * v1[q * 64 + lane];
+      bsk[(long long)col * ldb + r] -= s;
+    }
+  }
+}
+
+}  // namespace
+
+int launch_bupdate(hipStream_t s, int m, const double* a, long long lda, int i, int bb,
+                   const double* t, const double* wpart, int nsplit, double* wp, long long ldw,
+                   double* bsk, long long ldb, int c0, int ncols, const int* info) {
+  if (ncols <= 0) return RQ_OK;
+  if (bb > MAX_B) return RQ_ERR_LIMIT;
+  hipLaunchKernelGGL(k_bupdate, dim3((ncols + 63) / 64), dim3(BT), 0, s, m, a, lda, i, bb, t,
+                     wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info);
+  RQ_HIP_CHECK(hipGetLastError());
+  return RQ_OK;
+}
+
+}  // namespace rq

@@ -132,6 +132,24 @@ int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, const double *A, int lda, 
  * workspace the kernels ran with. */
 int rqrcp_check(rqrcp_handle h, void *ws);
 
+/* Per-phase timing for benchmarks.  While enabled, rqrcp_factor and
+ * rqrcp_sketch record a HIP event pair on the handle's stream around every
+ * kernel launch, tagged with its phase and the launch's algorithmic work
+ * (flops and HBM bytes of the operation it performs, not of padding). */
+#define RQRCP_PHASE_SKETCH 0  /* Omega and B = Omega A */
+#define RQRCP_PHASE_QRCP 1    /* partial QRCP of the sketch */
+#define RQRCP_PHASE_SWAP 2    /* column moves */
+#define RQRCP_PHASE_PANEL 3   /* panel QR + T */
+#define RQRCP_PHASE_TRAIL 4   /* fused trailing update */
+#define RQRCP_PHASE_BUPDATE 5 /* W' = T^T W, R12 and the sample update */
+#define RQRCP_PHASE_OTHER 6
+#define RQRCP_NPHASES 7
+int rqrcp_set_timing(rqrcp_handle h, int enable);
+/* Synchronizes the stream, then returns and clears the totals since the last
+ * read (host arrays of RQRCP_NPHASES entries, any may be NULL): elapsed
+ * milliseconds, number of launches, algorithmic flops and bytes. */
+int rqrcp_read_timing(rqrcp_handle h, double *ms, int *count, double *flops, double *bytes);
+
 /* Human-readable text of a status code (static storage). */
 const char *rqrcp_status_string(int status);
 

@@ -33,8 +33,9 @@ STATUS = {
 EXPORTS = (
     "rqrcp_create", "rqrcp_destroy", "rqrcp_set_stream", "rqrcp_workspace_size",
     "rqrcp_limits", "rqrcp_gaussian", "rqrcp_sketch", "rqrcp_factor", "rqrcp_form_q",
-    "rqrcp_check", "rqrcp_status_string",
+    "rqrcp_check", "rqrcp_status_string", "rqrcp_set_timing", "rqrcp_read_timing",
 )
+PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other")
 
 
 class Params(ctypes.Structure):
@@ -67,6 +68,9 @@ def load_library(path: str = LIB_PATH):
         "rqrcp_form_q": (i, [vp, i, i, i, vp, i, vp, vp, i, vp, sz]),
         "rqrcp_check": (i, [vp, vp]),
         "rqrcp_status_string": (ctypes.c_char_p, [i]),
+        "rqrcp_set_timing": (i, [vp, i]),
+        "rqrcp_read_timing": (i, [vp, P(ctypes.c_double), P(i), P(ctypes.c_double),
+                                  P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -246,6 +250,21 @@ def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=Fal
     return Factorization(af, jp, tau, bs, info, k, b)
 
 
+def factor_into(a, k, b, p, seed, jpvt, tau, bsk, info, ws, flags=0):
+    """rqrcp_factor on caller-owned device buffers (no allocation, no sync).
+
+    a: column-major float64 (m x n), overwritten; jpvt int32 (n); tau float64 (k);
+    bsk column-major float64 ((b+p) x n) or None with FROZEN_PIVOTS; info int32 (1);
+    ws uint8 workspace of at least workspace_bytes(m, n, k, b, p, flags).
+    """
+    m, n = a.shape
+    prm = Params(b, p, seed, F64, flags)
+    _check(load_library().rqrcp_factor(handle(), m, n, k, ctypes.byref(prm), _ptr(a), _ld(a),
+                                        _ptr(jpvt), _ptr(tau), _ptr(bsk),
+                                        (_ld(bsk) if bsk is not None else b + p), _ptr(info),
+                                        _ptr(ws), ws.numel()), "rqrcp_factor")
+
+
 def form_q(fact_a, tau, k=None, b=64, ws=None):
     """Explicit Q1 (m x k) of a factorization in LAPACK storage."""
     torch = _torch()
@@ -258,6 +277,21 @@ def form_q(fact_a, tau, k=None, b=64, ws=None):
                                         _ptr(q), max(1, m), _ptr(ws), ws.numel()),
            "rqrcp_form_q")
     return q
+
+
+def set_timing(enable: bool):
+    _check(load_library().rqrcp_set_timing(handle(), 1 if enable else 0), "rqrcp_set_timing")
+
+
+def read_timing():
+    """Per-phase totals since the last read: {phase: (ms, launches, flops, bytes)}."""
+    n = len(PHASES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int * n)()
+    fl = (ctypes.c_double * n)()
+    by = (ctypes.c_double * n)()
+    _check(load_library().rqrcp_read_timing(handle(), ms, cnt, fl, by), "rqrcp_read_timing")
+    return {PHASES[i]: (ms[i], cnt[i], fl[i], by[i]) for i in range(n)}
 
 
 def check(ws=None):

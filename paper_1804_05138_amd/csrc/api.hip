@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/rqrcp.h"
 #include "gemm.h"
@@ -27,7 +28,58 @@
 struct rqrcp_ctx {
   hipStream_t stream;
   int device;
+  // per-phase timing (benchmarks only)
+  struct Mark {
+    int phase;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  bool timing = false;
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  double ms[RQRCP_NPHASES] = {};
+  int count[RQRCP_NPHASES] = {};
+  double flops[RQRCP_NPHASES] = {};
+  double bytes[RQRCP_NPHASES] = {};
+
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
 };
+
+namespace {
+// Records an event pair around the launches issued during its lifetime.
+struct PhaseTimer {
+  rqrcp_ctx* h;
+  rqrcp_ctx::Mark mk;
+  bool on;
+  PhaseTimer(rqrcp_ctx* h_, int phase, double flops, double bytes) : h(h_), on(h_->timing) {
+    if (!on) return;
+    mk.phase = phase;
+    mk.flops = flops;
+    mk.bytes = bytes;
+    mk.a = h->event();
+    mk.b = h->event();
+    if (!mk.a || !mk.b) {
+      on = false;
+      return;
+    }
+    hipEventRecord(mk.a, h->stream);
+  }
+  ~PhaseTimer() {
+    if (!on) return;
+    hipEventRecord(mk.b, h->stream);
+    h->marks.push_back(mk);
+  }
+};
+}  // namespace
 
 namespace {
 
@@ -152,6 +204,11 @@ int rqrcp_create(rqrcp_handle* h, void* stream) {
 
 int rqrcp_destroy(rqrcp_handle h) {
   if (!h) return -1;
+  for (auto& mk : h->marks) {
+    hipEventDestroy(mk.a);
+    hipEventDestroy(mk.b);
+  }
+  for (auto e : h->pool) hipEventDestroy(e);
   delete h;
   return 0;
 }
@@ -165,11 +222,12 @@ int rqrcp_set_stream(rqrcp_handle h, void* stream) {
 int rqrcp_limits(int l, int* max_b, int* max_l, int* max_n) {
   if (max_b) *max_b = MAX_B;
   if (max_l) *max_l = MAX_L;
-  // one sketch column per thread (two for l > 48), one 256-thread workgroup per compute unit
+  // 256 sketch columns per workgroup, one workgroup per compute unit
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (max_n) *max_n = (l <= 48 ? 256 : 128) * ncu;
+  (void)l;
+  if (max_n) *max_n = 256 * ncu;
   return 0;
 }
 
@@ -274,25 +332,48 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, d
                        (const double*)cp, (long long)m, A, (long long)lda, (const int*)jpvt);
     RQ_HIP_CHECK(hipGetLastError());
   } else if (!(prm->flags & RQRCP_USER_SKETCH)) {
+    PhaseTimer pt(h, RQRCP_PHASE_SKETCH, 2.0 * l * (double)m * n,
+                  8.0 * ((double)m * n + (double)l * n));
     rc = launch_gaussian(s, l, m, prm->seed, 0, om, l);
     if (rc) return rc;
     rc = launch_sketch_f64(s, m, n, l, om, l, A, lda, B, ldb, spart);
     if (rc) return rc;
   }
 
+  // algorithmic work of one launch of each phase
+  auto qrcp_flops = [&](int nc, int steps) {
+    double f = 0.0;
+    for (int t = 0; t < steps; ++t) f += 4.0 * (l - t) * (double)(nc - t);
+    return f;
+  };
+  auto panel_flops = [&](int rows, int w, int wprev) {
+    return 3.0 * rows * (double)w * w + 2.0 * (rows + wprev) * (double)wprev * w;
+  };
+  auto trail_flops = [&](int ii, int bbu, int bbn, int ncols) {
+    return 2.0 * (m - ii) * (double)bbu * ncols + 2.0 * (m - ii - bbu) * (double)bbn * ncols;
+  };
+
   int i = 0;
   int bb = std::min(b, k);
   int nsp = 0;
   if (!frozen) {
-    rc = launch_qrcp_sketch(s, B, ldb, l, 0, n, bb, 0, qscr, cand, pairs, info);
-    if (rc) return rc;
+    {
+      PhaseTimer pt(h, RQRCP_PHASE_QRCP, qrcp_flops(n, bb), 16.0 * l * (double)n);
+      rc = launch_qrcp_sketch(s, B, ldb, l, 0, n, bb, 0, qscr, cand, pairs, info);
+      if (rc) return rc;
+    }
+    PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
     rc = launch_apply_pairs(s, m, A, lda, 0, jpvt, nullptr, 0, 0, 0, pairs, &qscr->npairs,
                             2 * bb, nullptr);
     if (rc) return rc;
   }
-  rc = launch_panel(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart);
-  if (rc) return rc;
   {
+    PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m, bb, 0), 16.0 * m * (double)bb);
+    rc = launch_panel(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart);
+    if (rc) return rc;
+  }
+  if (n - bb > 0) {
+    PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(0, 0, bb, n - bb), 8.0 * m * (double)(n - bb));
     TrailPlan pl = trail_plan(m, n - bb);
     rc = launch_trail_f64(s, m, A, lda, 0, 0, bb, nullptr, 0, 0, bb, n, wpart, pl.nsplit, &nsp);
     if (rc) return rc;
@@ -300,30 +381,53 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, d
   for (;;) {
     const int c0 = i + bb;
     const int ncols = n - c0;
-    rc = launch_bupdate(s, m, A, lda, i, bb, tmat, wpart, nsp, wp, ldw, frozen ? nullptr : B, ldb,
-                        c0, ncols, info);
-    if (rc) return rc;
+    if (ncols > 0) {
+      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * bb * (double)bb * ncols,
+                    8.0 * ncols * (double)bb * (nsp + 4));
+      rc = launch_bupdate(s, m, A, lda, i, bb, tmat, wpart, nsp, wp, ldw, frozen ? nullptr : B,
+                          ldb, c0, ncols, info);
+      if (rc) return rc;
+    }
     if (c0 < k) {
       const int bbn = std::min(b, k - c0);
       if (!frozen) {
-        rc = launch_qrcp_sketch(s, B, ldb, l, c0, ncols, bbn, c0, qscr, cand, pairs, info);
-        if (rc) return rc;
+        {
+          PhaseTimer pt(h, RQRCP_PHASE_QRCP, qrcp_flops(ncols, bbn), 16.0 * l * (double)ncols);
+          rc = launch_qrcp_sketch(s, B, ldb, l, c0, ncols, bbn, c0, qscr, cand, pairs, info);
+          if (rc) return rc;
+        }
+        PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
         rc = launch_apply_pairs(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs, &qscr->npairs,
                                 2 * bbn, nullptr);
         if (rc) return rc;
       }
-      rc = launch_panel(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart);
-      if (rc) return rc;
-      TrailPlan pl = trail_plan(m - i, n - (c0 + bbn));
-      rc = launch_trail_f64(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw, c0 + bbn,
-                            c0 + bbn, n, wpart, pl.nsplit, &nsp);
-      if (rc) return rc;
+      {
+        PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m - c0, bbn, bb),
+                      16.0 * (m - i) * (double)bbn);
+        rc = launch_panel(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart);
+        if (rc) return rc;
+      }
+      const int nrest = n - (c0 + bbn);
+      if (nrest > 0) {
+        PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, bbn, nrest),
+                      16.0 * (m - i) * (double)nrest);
+        TrailPlan pl = trail_plan(m - i, nrest);
+        rc = launch_trail_f64(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw, c0 + bbn,
+                              c0 + bbn, n, wpart, pl.nsplit, &nsp);
+        if (rc) return rc;
+      } else {
+        nsp = 0;
+      }
       i = c0;
       bb = bbn;
     } else {
-      int dummy = 0;
-      rc = launch_trail_f64(s, m, A, lda, i, bb, 0, wp, ldw, c0, c0, n, nullptr, 1, &dummy);
-      if (rc) return rc;
+      if (ncols > 0) {
+        PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, 0, ncols),
+                      16.0 * (m - i) * (double)ncols);
+        int dummy = 0;
+        rc = launch_trail_f64(s, m, A, lda, i, bb, 0, wp, ldw, c0, c0, n, nullptr, 1, &dummy);
+        if (rc) return rc;
+      }
       break;
     }
   }
@@ -362,6 +466,40 @@ int rqrcp_check(rqrcp_handle h, void* ws) {
     hipMemcpy(w + QSCR_OFF, zero, sizeof(zero), hipMemcpyHostToDevice);
     hipMemcpy(w + PSCR_OFF, zero, sizeof(zero), hipMemcpyHostToDevice);
     return RQRCP_ERR_BARRIER;
+  }
+  return 0;
+}
+
+int rqrcp_set_timing(rqrcp_handle h, int enable) {
+  if (!h) return -1;
+  h->timing = enable != 0;
+  return 0;
+}
+
+int rqrcp_read_timing(rqrcp_handle h, double* ms, int* count, double* flops, double* bytes) {
+  if (!h) return -1;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return RQRCP_ERR_HIP;
+  for (auto& mk : h->marks) {
+    float e = 0.0f;
+    if (hipEventElapsedTime(&e, mk.a, mk.b) == hipSuccess) {
+      h->ms[mk.phase] += e;
+      h->count[mk.phase] += 1;
+      h->flops[mk.phase] += mk.flops;
+      h->bytes[mk.phase] += mk.bytes;
+    }
+    h->pool.push_back(mk.a);
+    h->pool.push_back(mk.b);
+  }
+  h->marks.clear();
+  for (int p = 0; p < RQRCP_NPHASES; ++p) {
+    if (ms) ms[p] = h->ms[p];
+    if (count) count[p] = h->count[p];
+    if (flops) flops[p] = h->flops[p];
+    if (bytes) bytes[p] = h->bytes[p];
+    h->ms[p] = 0.0;
+    h->count[p] = 0;
+    h->flops[p] = 0.0;
+    h->bytes[p] = 0.0;
   }
   return 0;
 }

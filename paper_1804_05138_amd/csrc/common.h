@@ -114,6 +114,9 @@ struct GridBarrier {
 RQ_DEV unsigned atomic_load_agent(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+RQ_DEV unsigned atomic_peek_agent(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Per-workgroup barrier state kept in LDS.
 struct BarrierLocal {
@@ -123,16 +126,17 @@ struct BarrierLocal {
 
 // Phase 1 (all threads): arrive.  Returns true in every thread of the last
 // workgroup to arrive; that workgroup then sees every other workgroup's
-// global writes made before their arrival.
+// global writes made before their arrival.  The arrival is one release
+// RMW (it orders this workgroup's earlier writes and the read of the
+// generation before the increment) with acquire semantics for the last.
 RQ_DEV bool grid_arrive(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned g0 = atomic_load_agent(&bar->gen);
-    __threadfence();
-    const unsigned arrived = atomicAdd(&bar->count, 1u);
+    const unsigned g0 = atomic_peek_agent(&bar->gen);
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     bl->g0 = g0;
     bl->last = (arrived == nwg - 1) ? 1u : 0u;
-    __threadfence();
   }
   __syncthreads();
   return bl->last != 0;
@@ -142,26 +146,26 @@ RQ_DEV bool grid_arrive(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {
 RQ_DEV void grid_release(GridBarrier* bar) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
     __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
 }
 
-// Phase 2b (all threads of the other workgroups): bounded wait.
+// Phase 2b (all threads of the other workgroups): bounded wait.  Polls with
+// relaxed loads; one acquire fence once the generation has moved.
 RQ_DEV void grid_wait(GridBarrier* bar, const BarrierLocal* bl) {
   if (threadIdx.x == 0) {
     unsigned spins = 0;
-    while (atomic_load_agent(&bar->gen) == bl->g0) {
+    while (atomic_peek_agent(&bar->gen) == bl->g0) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > RQ_SPIN_LIMIT) {
         atomicOr(&bar->err, 1u);
         break;
       }
-      if ((spins & 1023u) == 0 && atomic_load_agent(&bar->err)) break;
+      if ((spins & 1023u) == 0 && atomic_peek_agent(&bar->err)) break;
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }

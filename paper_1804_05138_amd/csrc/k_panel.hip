@@ -36,6 +36,7 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
   __shared__ double s_row[MAX_B];
   __shared__ double s_S[MAX_B];
   __shared__ double s_f[MAX_B];
+  __shared__ double s_g[MAX_B];
   __shared__ double s_hh[3];
   __shared__ BarrierLocal bl;
 
@@ -82,16 +83,18 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
     }
   }
 
-  const int ng = PT / bb;  // row groups in the dot-product phase
+  const int ng = PT / bb;  // row groups: thread (c, q) works on column c, rows q, q+ng, ...
+  const int cc = tid % bb, qq0 = tid / bb;
   for (int t = 0; t < bb; ++t) {
     const int gr = i + t;
+    // first local row strictly below the diagonal row, in my row group
+    const int lo = max(0, gr - rs + 1);
+    const int lr0 = lo + (((qq0 - lo) % ng) + ng) % ng;
     // ---- partial dot products over my rows below the diagonal ----
     {
-      const int c = tid % bb, q = tid / bb;
       double acc = 0.0;
-      if (q < ng) {
-        for (int lr = q; lr < nr; lr += ng)
-          if (rs + lr > gr) acc += P[lr * ldp + t] * P[lr * ldp + c];
+      if (qq0 < ng) {
+        for (int lr = lr0; lr < nr; lr += ng) acc += P[lr * ldp + t] * P[lr * ldp + cc];
       }
       s_red[tid] = acc;
       __syncthreads();
@@ -106,8 +109,18 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
     if (grid_arrive(bar, G, &bl)) {
       const int c = tid % bb, q = tid / bb;
       double acc = 0.0;
-      if (q < ng)
-        for (int gg = q; gg < G; gg += ng) acc += gpart[(size_t)gg * bb + c];
+      if (q < ng) {
+        // independent loads in flight together (the partials come from other XCDs)
+        int gg = q;
+        for (; gg + 7 * ng < G; gg += 8 * ng) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = gpart[(size_t)(gg + u * ng) * bb + c];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; gg < G; gg += ng) acc += gpart[(size_t)gg * bb + c];
+      }
       s_red[tid] = acc;
       __syncthreads();
       if (tid < bb) {
@@ -159,18 +172,18 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
     }
     __syncthreads();
     const double beta = s_hh[0], tt = s_hh[1], den = s_hh[2];
-    // s_f[c] = tau * (v^T a_c) for c > t
-    if (tid < bb) s_f[tid] = (tid > t && tt != 0.0) ? tt * (s_row[tid] + s_S[tid] / den) : 0.0;
+    // s_f[c] = tau * (v^T a_c) for c > t; s_g[c] = s_f[c] / (alpha - beta)
+    if (tid < bb) {
+      const double f = (tid > t && tt != 0.0) ? tt * (s_row[tid] + s_S[tid] / den) : 0.0;
+      s_f[tid] = f;
+      s_g[tid] = f / den;
+    }
     __syncthreads();
     if (tt != 0.0) {
-      for (int e = tid; e < nr * bb; e += PT) {
-        const int lr = e / bb, c = e % bb;
-        const int gro = rs + lr;
-        if (c <= t || gro < gr) continue;
-        if (gro == gr)
-          P[lr * ldp + c] -= s_f[c];
-        else
-          P[lr * ldp + c] -= (P[lr * ldp + t] / den) * s_f[c];
+      if (qq0 < ng && cc > t) {
+        const double g = s_g[cc];
+        for (int lr = lr0; lr < nr; lr += ng) P[lr * ldp + cc] -= P[lr * ldp + t] * g;
+        if (gr >= rs && gr < re && qq0 == 0) P[(gr - rs) * ldp + cc] -= s_f[cc];
       }
       __syncthreads();
     }
@@ -248,12 +261,11 @@ int launch_panel(hipStream_t s, int m, double* a, long long lda, int i, int bb, 
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   RQ_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu, reinterpret_cast<const void*>(&k_panel), PT, shmem));
+  // the grid barrier needs every workgroup resident at once
   if (G > ncu * per_cu) return RQ_ERR_LIMIT;
-  GridBarrier* bar = &scr->bar;
-  int Rv = R;
-  void* args[] = {&m, &a, &lda, &i, &bb, &bbp, &wp, &ldw, &tau, &t, &bar, &partial, &Rv};
-  RQ_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_panel), dim3(G),
-                                          dim3(PT), args, shmem, s));
+  hipLaunchKernelGGL(k_panel, dim3(G), dim3(PT), shmem, s, m, a, lda, i, bb, bbp, wp, ldw, tau, t,
+                     &scr->bar, partial, R);
+  RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
 

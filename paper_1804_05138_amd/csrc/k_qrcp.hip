@@ -19,8 +19,6 @@
 namespace rq {
 namespace {
 
-constexpr int QT = 256;
-
 RQ_DEV bool better(double n1, int p1, double n2, int p2) {
   return n1 > n2 || (n1 == n2 && p1 < p2);
 }
@@ -45,7 +43,8 @@ RQ_DEV double tpc_sum(double v) {
   return v;
 }
 
-template <int RPT, int TPC>
+// QT threads per workgroup; every workgroup holds CPW = QT / TPC = 256 columns.
+template <int RPT, int TPC, int QT>
 __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
     double* __restrict__ bsk, long long ldb, int l, int nc, int nsteps, int gstep0,
     GridBarrier* bar, double* __restrict__ cand, int cs, int* __restrict__ pairs,
@@ -273,35 +272,35 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
 template <int RPT, int TPC>
 int launch_t(hipStream_t s, double* b, long long ldb, int l, int nc, int nsteps, int gstep0,
              QrcpScratch* scr, double* cand, int* pairs, int* info) {
+  constexpr int QT = 256 * TPC;
   constexpr int CPW = QT / TPC;
+  auto kern = &k_qrcp_sketch<RPT, TPC, QT>;
   const int G = (nc + CPW - 1) / CPW;
   const int cs = ((l + 4) + 7) / 8 * 8;
   int dev = 0, ncu = 0, per_cu = 0;
   RQ_HIP_CHECK(hipGetDevice(&dev));
   RQ_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   RQ_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(&k_qrcp_sketch<RPT, TPC>), QT, 0));
+      &per_cu, reinterpret_cast<const void*>(kern), QT, 0));
+  // the grid barrier needs every workgroup resident at once
   if (G > ncu * per_cu) return RQ_ERR_LIMIT;
-  GridBarrier* bar = &scr->bar;
-  int* npairs = &scr->npairs;
-  void* args[] = {&b, &ldb, &l, &nc, &nsteps, &gstep0, &bar, &cand, (void*)&cs, &pairs,
-                  &npairs, &info};
-  RQ_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_qrcp_sketch<RPT, TPC>),
-                                          dim3(G), dim3(QT), args, 0, s));
+  hipLaunchKernelGGL(kern, dim3(G), dim3(QT), 0, s, b, ldb, l, nc, nsteps, gstep0, &scr->bar, cand,
+                     cs, pairs, &scr->npairs, info);
+  RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
 
 }  // namespace
 
 size_t qrcp_cand_doubles(int l, int nc) {
-  const int cpw = (l <= 48) ? QT : QT / 2;
+  const int cpw = 256;
   const size_t G = (size_t)(nc + cpw - 1) / cpw;
   const size_t cs = ((l + 4) + 7) / 8 * 8;
   return 2 * G * cs;
 }
 
 int qrcp_sketch_grid(int l, int nc) {
-  const int cpw = (l <= 48) ? QT : QT / 2;
+  const int cpw = 256;
   return (nc + cpw - 1) / cpw;
 }
 

@@ -24,16 +24,26 @@ namespace rq {
 namespace {
 
 constexpr int TT = 256;
-constexpr int TR = 64;  // rows per tile
+constexpr int TR = 32;  // rows per tile
+
+// LDS layouts (no padding; the XOR swizzles make both the row-contiguous
+// staging stores and the MFMA operand reads free of bank conflicts per
+// half-wave):
+//   V_i   staged transposed, element (r, q) at q*TR + (r ^ 16*(q & 1))
+//   V_i+1 staged by rows,    element (r, q) at r*BBM + (q ^ swz(r)),
+//         swz(r) = ((r >> 1) & 15) | ((r & 1) << 4)
+RQ_DEV int swz_n(int r) { return ((r >> 1) & 15) | ((r & 1) << 4); }
 
 template <int BBM>
-__global__ __launch_bounds__(TT, 2) void k_trail_f64(
+__global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
     int m, double* __restrict__ a, long long lda, int i, int bbu, int bbn,
     const double* __restrict__ wp, long long ldw, int w0, int c_begin, int c_end,
     double* __restrict__ wpart, int rows_per_split) {
-  constexpr int LDV = BBM + 2;
-  __shared__ double sVu[TR * LDV];
-  __shared__ double sVn[TR * LDV];
+  static_assert(BBM % 32 == 0, "block width must be a multiple of 32");
+  constexpr int QS = TT / TR;       // reflector columns staged per pass of the block
+  constexpr int NQ = BBM / QS;      // reflector values staged per thread and matrix
+  __shared__ double sVuT[BBM * TR];
+  __shared__ double sVn[TR * BBM];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr16 = lane & 15, lg = lane >> 4;
@@ -54,51 +64,68 @@ __global__ __launch_bounds__(TT, 2) void k_trail_f64(
   for (int qb = 0; qb < BBM / 16; ++qb) acc[qb] = v4d{0.0, 0.0, 0.0, 0.0};
 
   double* acol = a + (long long)col * lda;
-  for (int r0 = ri0; r0 < ri1; r0 += TR) {
-    // ---- stage the reflector rows of this tile (unit lower trapezoidal) ----
-    {
-      const int rr = tid & 63;
-      const int r = r0 + rr;
-      for (int q = tid >> 6; q < BBM; q += TT / 64) {
-        double vu = 0.0, vn = 0.0;
-        if (r < m) {
-          if (q < bbu) {
-            const int d = r - i;
-            vu = (d > q) ? a[(long long)(i + q) * lda + r] : (d == q ? 1.0 : 0.0);
-          }
-          if (q < bbn) {
-            const int d = r - in;
-            vn = (d > q) ? a[(long long)(in + q) * lda + r] : (d == q ? 1.0 : 0.0);
-          }
-        }
-        sVu[rr * LDV + q] = vu;
-        sVn[rr * LDV + q] = vn;
-      }
-    }
-    // ---- the tile slab of this wave, in accumulator layout ----
-    v4d d[4];
+  // this thread's share of a tile's reflector rows: row rr, columns q0 + QS*j
+  const int rr = tid % TR, q0 = tid / TR;
+  double pu[NQ], pn[NQ];
+  auto fetch_v = [&](int r0) {
+    const int r = r0 + rr;
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int j = 0; j < NQ; ++j) {
+      const int q = q0 + QS * j;
+      double vu = 0.0, vn = 0.0;
+      if (r < m) {
+        const int du = r - i, dv = r - in;
+        if (q < bbu) vu = (du > q) ? a[(long long)(i + q) * lda + r] : (du == q ? 1.0 : 0.0);
+        if (q < bbn) vn = (dv > q) ? a[(long long)(in + q) * lda + r] : (dv == q ? 1.0 : 0.0);
+      }
+      pu[j] = vu;
+      pn[j] = vn;
+    }
+  };
+  // this wave's 16 columns of a tile, in accumulator layout
+  auto fetch_a = [&](int r0, v4d* dd) {
+#pragma unroll
+    for (int b = 0; b < TR / 16; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = r0 + 16 * b + acc_row<double>(lg, e);
-        d[b][e] = (colok && row < ri1) ? acol[row] : 0.0;
+        dd[b][e] = (colok && row < ri1) ? acol[row] : 0.0;
       }
+  };
+
+  v4d d[TR / 16], dn[TR / 16];
+  fetch_v(ri0);
+  fetch_a(ri0, d);
+  for (int r0 = ri0; r0 < ri1; r0 += TR) {
+    // ---- stage this tile's reflector rows (fetched one tile ahead) ----
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int q = q0 + QS * j;
+      sVuT[q * TR + (rr ^ ((q & 1) << 4))] = pu[j];
+      sVn[rr * BBM + (q ^ swz_n(rr))] = pn[j];
+    }
     __syncthreads();
+    // ---- fetch the next tile while this one is on the MFMAs ----
+    const bool more = r0 + TR < ri1;
+    if (more) {
+      fetch_v(r0 + TR);
+      fetch_a(r0 + TR, dn);
+    }
 
     if (bbu > 0) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int kq = 0; kq < BBM / 4; ++kq) {
+        if (4 * kq < bbu) {
+          const int q = 4 * kq + lg;
 #pragma unroll
-        for (int kq = 0; kq < BBM / 4; ++kq) {
-          if (4 * kq < bbu) {
-            const double av = sVu[(16 * b + lr16) * LDV + 4 * kq + lg];
+          for (int b = 0; b < TR / 16; ++b) {
+            const double av = sVuT[q * TR + ((16 * b + lr16) ^ ((q & 1) << 4))];
             d[b] = mfma_f64(av, bw[kq], d[b]);
           }
         }
       }
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < TR / 16; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = r0 + 16 * b + acc_row<double>(lg, e);
@@ -107,19 +134,24 @@ __global__ __launch_bounds__(TT, 2) void k_trail_f64(
     }
     if (bbn > 0) {
 #pragma unroll
-      for (int qb = 0; qb < BBM / 16; ++qb) {
-        if (16 * qb < bbn) {
+      for (int b = 0; b < TR / 16; ++b)
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
+        for (int e = 0; e < 4; ++e) {
+          const int r = 16 * b + acc_row<double>(lg, e);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const double av = sVn[(16 * b + acc_row<double>(lg, e)) * LDV + 16 * qb + lr16];
+          for (int qb = 0; qb < BBM / 16; ++qb) {
+            if (16 * qb < bbn) {
+              const double av = sVn[r * BBM + ((16 * qb + lr16) ^ swz_n(r))];
               acc[qb] = mfma_f64(av, d[b][e], acc[qb]);
             }
+          }
         }
-      }
     }
     __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int b = 0; b < TR / 16; ++b) d[b] = dn[b];
+    }
   }
 
   if (bbn > 0 && colok) {

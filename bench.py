@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-k", type=int, default=256)
+    ap.add_argument("--matrix", choices=("lowrank", "gaussian"), default="lowrank",
+                    help="gaussian: i.i.d. N(0,1) A of the same size (no QR in the generator; "
+                         "for profiler runs, where kernel times depend only on the sizes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
@@ -95,12 +98,15 @@ def main():
     import torch
     import paper_1804_05138_amd as rq
     from paper_1804_05138_amd.flops import qr_equivalent_flops, rqrcp_flops
-    from workloads import lowrank_torch, sigma_pow
+    from workloads import gaussian_torch, lowrank_torch, sigma_pow
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
-    a0 = lowrank_torch(M, N, sigma_pow(N, 1.5), SEED, device=dev)
+    if args.matrix == "lowrank":
+        a0 = lowrank_torch(M, N, sigma_pow(N, 1.5), SEED, device=dev)
+    else:
+        a0 = gaussian_torch(M, N, SEED, device=dev)
     assert a0.stride(0) == 1
     torch.cuda.synchronize()
     log(f"generated A {M}x{N} in {time.perf_counter() - t0:.1f} s")
@@ -155,8 +161,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "plain FP64 truncated RQRCP of a 16384x16384 matrix with "
-                               "sigma_j = j^-1.5 and Haar U, V; k=1024, b=64, p=8",
+        "config": {"workload": ("plain FP64 truncated RQRCP of a 16384x16384 matrix with "
+                                "sigma_j = j^-1.5 and Haar U, V; k=1024, b=64, p=8")
+                               if args.matrix == "lowrank" else
+                               "plain FP64 truncated RQRCP of a 16384x16384 i.i.d. N(0,1) "
+                               "matrix; k=1024, b=64, p=8 (profiling input)",
                    "m": M, "n": N, "k": K, "b": B, "p": P, "seed": SEED,
                    "flops_per_step": flops,
                    "qr_equivalent_tflops": round(qr_equivalent_flops(M, N, K) / (ms_step / 1e3) / 1e12, 3)},

@@ -149,8 +149,14 @@ Layout layout(int m, int n, int k, int b, int p, unsigned flags) {
   return L;
 }
 
-__global__ void k_init(QrcpScratch* q, PanelScratch* p, int* info, int* jpvt, int n, int iota) {
+// Clears the scratch words of one factorization.  The candidate records of the
+// sketch QRCP carry a sequence number (the global pivot step + 1) that tells
+// readers a record is current; zeroing them keeps a record left by an earlier
+// call on the same workspace from passing for one of this call.
+__global__ void k_init(QrcpScratch* q, PanelScratch* p, int* info, int* jpvt, int n, int iota,
+                       double* cand, long long ncand) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long e = t; e < ncand; e += (long long)gridDim.x * blockDim.x) cand[e] = 0.0;
   if (t == 0) {
     q->bar.count = 0;
     q->bar.err = 0;
@@ -321,7 +327,7 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, d
   int rc;
 
   hipLaunchKernelGGL(k_init, dim3(grid_for(n)), dim3(256), 0, s, qscr, pscr, info, jpvt, n,
-                     frozen ? 0 : 1);
+                     frozen ? 0 : 1, cand, frozen ? 0LL : (long long)qrcp_cand_doubles(l, n));
   RQ_HIP_CHECK(hipGetLastError());
 
   if (frozen) {

@@ -118,24 +118,28 @@ RQ_DEV unsigned atomic_peek_agent(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Per-workgroup barrier state kept in LDS.
+// Per-workgroup barrier state kept in LDS: the generation this workgroup
+// waits to see move, tracked locally so that arriving needs no extra read.
 struct BarrierLocal {
-  unsigned g0;
+  unsigned gen;
   unsigned last;
 };
 
-// Phase 1 (all threads): arrive.  Returns true in every thread of the last
-// workgroup to arrive; that workgroup then sees every other workgroup's
-// global writes made before their arrival.  The arrival is one release
-// RMW (it orders this workgroup's earlier writes and the read of the
-// generation before the increment) with acquire semantics for the last.
+// Once per launch, by all threads, before the first barrier of the launch
+// (safe: no barrier of this launch can complete before this workgroup arrives).
+RQ_DEV void grid_sync_init(GridBarrier* bar, BarrierLocal* bl) {
+  if (threadIdx.x == 0) bl->gen = atomic_peek_agent(&bar->gen);
+  __syncthreads();
+}
+
+// Phase 1 (all threads): arrive with one acquire-release RMW.  Returns true in
+// every thread of the last workgroup to arrive, which then sees every other
+// workgroup's global writes made before their arrival.
 RQ_DEV bool grid_arrive(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned g0 = atomic_peek_agent(&bar->gen);
     const unsigned arrived =
         __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    bl->g0 = g0;
     bl->last = (arrived == nwg - 1) ? 1u : 0u;
   }
   __syncthreads();
@@ -143,21 +147,22 @@ RQ_DEV bool grid_arrive(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {
 }
 
 // Phase 2a (all threads of the last workgroup): release the others.
-RQ_DEV void grid_release(GridBarrier* bar) {
+RQ_DEV void grid_release(GridBarrier* bar, BarrierLocal* bl) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    bl->gen += 1u;
   }
   __syncthreads();
 }
 
 // Phase 2b (all threads of the other workgroups): bounded wait.  Polls with
 // relaxed loads; one acquire fence once the generation has moved.
-RQ_DEV void grid_wait(GridBarrier* bar, const BarrierLocal* bl) {
+RQ_DEV void grid_wait(GridBarrier* bar, BarrierLocal* bl) {
   if (threadIdx.x == 0) {
     unsigned spins = 0;
-    while (atomic_peek_agent(&bar->gen) == bl->g0) {
+    while (atomic_peek_agent(&bar->gen) == bl->gen) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > RQ_SPIN_LIMIT) {
         atomicOr(&bar->err, 1u);
@@ -166,15 +171,121 @@ RQ_DEV void grid_wait(GridBarrier* bar, const BarrierLocal* bl) {
       if ((spins & 1023u) == 0 && atomic_peek_agent(&bar->err)) break;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    bl->gen += 1u;
   }
   __syncthreads();
 }
 
+// Publish-and-poll exchange: a workgroup publishes a record by writing it and
+// then storing `seq` into the record's sequence word with release semantics
+// (called by thread 0 after a workgroup barrier, so every thread's record
+// writes are ordered before it).  Readers wait until the sequence words of
+// all `n` records (stride `stride` 32-bit words) equal `seq`, then acquire.
+// One workgroup-wide barrier; no shared counter, so no atomic contention.
+RQ_DEV void publish_seq(unsigned* seqword, unsigned seq) {
+  __hip_atomic_store(seqword, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+RQ_DEV void wait_all_seq(const unsigned* seq0, long long stride, int n, unsigned seq,
+                         GridBarrier* bar) {
+  if ((threadIdx.x >> 6) == 0) {
+    const int lane = threadIdx.x & 63;
+    for (int q = lane; q < n; q += 64) {
+      const unsigned* w = seq0 + (long long)q * stride;
+      unsigned spins = 0;
+      while (atomic_peek_agent(w) != seq) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > RQ_SPIN_LIMIT) {
+          atomicOr(&bar->err, 1u);
+          break;
+        }
+        if ((spins & 1023u) == 0 && atomic_peek_agent(&bar->err)) break;
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 RQ_DEV void grid_barrier(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {
   if (grid_arrive(bar, nwg, bl))
-    grid_release(bar);
+    grid_release(bar, bl);
   else
     grid_wait(bar, bl);
+}
+
+// ---------------------------------------------------------------------------
+// Wave-wide reductions with DPP (data-parallel primitives of the VALU: row
+// shifts within 16-lane rows, then row broadcasts).  The inclusive scan
+// pattern row_shr 1,2,4,8 + row_bcast 15,31 leaves the total in lane 63,
+// which readlane then broadcasts.  Much cheaper than LDS-routed shuffles.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND_ZERO>
+RQ_DEV double dpp_f64(double old, double v) {
+  const long long ov = __double_as_longlong(old), vv = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)ov, (int)vv, CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO);
+  const int hi = __builtin_amdgcn_update_dpp((int)(ov >> 32), (int)(vv >> 32), CTRL, ROW_MASK,
+                                             BANK_MASK, BOUND_ZERO);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND_ZERO>
+RQ_DEV int dpp_i32(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO);
+}
+RQ_DEV double readlane_f64(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// DPP controls (GCN/CDNA encoding)
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114,
+              DPP_ROW_SHR8 = 0x118, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143,
+              DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+
+// Sum over the wave, returned in every lane.  The summation order is fixed.
+RQ_DEV double wave_sum_dpp(double v) {
+  v += dpp_f64<DPP_ROW_SHR1, 0xf, 0xf, true>(0.0, v);
+  v += dpp_f64<DPP_ROW_SHR2, 0xf, 0xf, true>(0.0, v);
+  v += dpp_f64<DPP_ROW_SHR4, 0xf, 0xe, true>(0.0, v);
+  v += dpp_f64<DPP_ROW_SHR8, 0xf, 0xc, true>(0.0, v);
+  v += dpp_f64<DPP_ROW_BCAST15, 0xa, 0xf, false>(0.0, v);
+  v += dpp_f64<DPP_ROW_BCAST31, 0xc, 0xf, false>(0.0, v);
+  return readlane_f64(v, 63);
+}
+
+// Sum of adjacent lane pairs (lane ^ 1), returned in both lanes.
+RQ_DEV double pair_sum_dpp(double v) {
+  return v + dpp_f64<DPP_QUAD_XOR1, 0xf, 0xf, false>(v, v);
+}
+
+// Arg-max over the wave of (n, then lowest p); s is carried along.  The
+// result is returned in every lane.  Lanes with no candidate pass n < 0.
+RQ_DEV bool argbetter(double n1, int p1, double n2, int p2) {
+  return n1 > n2 || (n1 == n2 && p1 < p2);
+}
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+RQ_DEV void argmax_step(double& n, int& p, int& s) {
+  // disabled / out-of-row lanes read their own value (old = own), a no-op
+  const double n2 = dpp_f64<CTRL, ROW_MASK, BANK_MASK, false>(n, n);
+  const int p2 = dpp_i32<CTRL, ROW_MASK, BANK_MASK, false>(p, p);
+  const int s2 = dpp_i32<CTRL, ROW_MASK, BANK_MASK, false>(s, s);
+  if (argbetter(n2, p2, n, p)) {
+    n = n2;
+    p = p2;
+    s = s2;
+  }
+}
+RQ_DEV void wave_argmax(double& n, int& p, int& s) {
+  argmax_step<DPP_ROW_SHR1, 0xf, 0xf>(n, p, s);
+  argmax_step<DPP_ROW_SHR2, 0xf, 0xf>(n, p, s);
+  argmax_step<DPP_ROW_SHR4, 0xf, 0xe>(n, p, s);
+  argmax_step<DPP_ROW_SHR8, 0xf, 0xc>(n, p, s);
+  argmax_step<DPP_ROW_BCAST15, 0xa, 0xf>(n, p, s);
+  argmax_step<DPP_ROW_BCAST31, 0xc, 0xf>(n, p, s);
+  n = readlane_f64(n, 63);
+  p = __builtin_amdgcn_readlane(p, 63);
+  s = __builtin_amdgcn_readlane(s, 63);
 }
 
 // ---------------------------------------------------------------------------

@@ -37,6 +37,7 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
   __shared__ double s_S[MAX_B];
   __shared__ double s_f[MAX_B];
   __shared__ double s_g[MAX_B];
+  (void)s_f;
   __shared__ double s_hh[3];
   __shared__ BarrierLocal bl;
 
@@ -45,9 +46,9 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
   const int rs = rp + g * R;
   const int re = min(m, rs + R);
   const int nr = max(0, re - rs);
-  double* growbuf = gpart + (size_t)G * bb;  // [2][bb]
-  double* gsbuf = growbuf + 2 * bb;          // [2][bb]
-  double* gz = gsbuf + 2 * bb;               // [bb][bb]
+  double* growbuf = gpart + 2 * (size_t)G * bb;  // [2][bb] pivot rows
+  double* gz = growbuf + 2 * bb;                 // [bb][bb] columns V^T v_t for T
+  grid_sync_init(bar, &bl);
 
   // ---- load the slab ----
   for (int e = tid; e < nr * bb; e += PT) {
@@ -90,6 +91,7 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
     // first local row strictly below the diagonal row, in my row group
     const int lo = max(0, gr - rs + 1);
     const int lr0 = lo + (((qq0 - lo) % ng) + ng) % ng;
+    double* gp = gpart + (size_t)(t & 1) * G * bb;  // partials of this step
     // ---- partial dot products over my rows below the diagonal ----
     {
       double acc = 0.0;
@@ -101,60 +103,33 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
       if (tid < bb) {
         double sum = 0.0;
         for (int qq = 0; qq < ng; ++qq) sum += s_red[qq * bb + tid];
-        gpart[(size_t)g * bb + tid] = sum;
+        gp[(size_t)g * bb + tid] = sum;
       }
       if (gr >= rs && gr < re && tid < bb) growbuf[(t & 1) * bb + tid] = P[(gr - rs) * ldp + tid];
     }
-    // ---- global sum (last workgroup, fixed order) ----
-    if (grid_arrive(bar, G, &bl)) {
-      const int c = tid % bb, q = tid / bb;
+    grid_barrier(bar, G, &bl);
+    // ---- every workgroup adds all partials in the same fixed order ----
+    {
       double acc = 0.0;
-      if (q < ng) {
-        // independent loads in flight together (the partials come from other XCDs)
-        int gg = q;
-        for (; gg + 7 * ng < G; gg += 8 * ng) {
-          double v[8];
+      if (qq0 < ng) {
+        int gg = qq0;
+        for (; gg + 15 * ng < G; gg += 16 * ng) {
+          double v[16];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) v[u] = gpart[(size_t)(gg + u * ng) * bb + c];
+          for (int u = 0; u < 16; ++u) v[u] = gp[(size_t)(gg + u * ng) * bb + cc];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc += v[u];
+          for (int u = 0; u < 16; ++u) acc += v[u];
         }
-        for (; gg < G; gg += ng) acc += gpart[(size_t)gg * bb + c];
+        for (; gg < G; gg += ng) acc += gp[(size_t)gg * bb + cc];
       }
       s_red[tid] = acc;
+      if (tid < bb) s_row[tid] = growbuf[(t & 1) * bb + tid];
       __syncthreads();
       if (tid < bb) {
         double sum = 0.0;
         for (int qq = 0; qq < ng; ++qq) sum += s_red[qq * bb + tid];
         s_S[tid] = sum;
-        s_row[tid] = growbuf[(t & 1) * bb + tid];
       }
-      __syncthreads();
-      if (tid == 0) {
-        const double alpha = s_row[t], xn2 = s_S[t];
-        double beta = alpha, tt = 0.0, den = 1.0;
-        if (xn2 > 0.0) {
-          const double nrm = hypot(alpha, sqrt(xn2));
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          tt = (beta - alpha) / beta;
-          den = alpha - beta;
-        }
-        tau[i + t] = tt;
-        s_hh[2] = den;
-      }
-      __syncthreads();
-      if (tid < bb) {
-        gsbuf[(t & 1) * bb + tid] = s_S[tid];
-        gz[t * bb + tid] = (tid < t) ? (s_row[tid] + s_S[tid] / s_hh[2]) : 0.0;
-      }
-      grid_release(bar);
-    } else {
-      grid_wait(bar, &bl);
-    }
-    // ---- every workgroup forms the same reflector ----
-    if (tid < bb) {
-      s_S[tid] = gsbuf[(t & 1) * bb + tid];
-      s_row[tid] = growbuf[(t & 1) * bb + tid];
     }
     __syncthreads();
     if (tid == 0) {
@@ -169,9 +144,11 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
       s_hh[0] = beta;
       s_hh[1] = tt;
       s_hh[2] = den;
+      if (g == 0) tau[i + t] = tt;
     }
     __syncthreads();
     const double beta = s_hh[0], tt = s_hh[1], den = s_hh[2];
+    if (g == 0 && tid < bb) gz[t * bb + tid] = (tid < t) ? (s_row[tid] + s_S[tid] / den) : 0.0;
     // s_f[c] = tau * (v^T a_c) for c > t; s_g[c] = s_f[c] / (alpha - beta)
     if (tid < bb) {
       const double f = (tid > t && tt != 0.0) ? tt * (s_row[tid] + s_S[tid] / den) : 0.0;
@@ -203,9 +180,10 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
     a[(long long)(i + c) * lda + rs + r] = P[r * ldp + c];
   }
 
-  // ---- T from the stored (V^T v_t) columns (forward, columnwise) ----
-  grid_barrier(bar, G, &bl);
+  // ---- T from the stored (V^T v_t) columns (forward, columnwise); workgroup 0
+  // wrote every tau and gz entry itself ----
   if (g == 0) {
+    __syncthreads();
     double* T = s_red;  // bb <= 128 needs bb*bb doubles: use the panel slab instead
     T = P;
     for (int e = tid; e < bb * bb; e += PT) T[e] = 0.0;
@@ -237,7 +215,7 @@ static int panel_rows_per_wg(int bb, int bbp) {
 size_t panel_partial_doubles(int rows, int bb) {
   const int R = panel_rows_per_wg(bb, MAX_B);
   const size_t G = (size_t)(rows + R - 1) / R;
-  return G * bb + 4 * (size_t)bb + (size_t)bb * bb + 64;
+  return 2 * G * bb + 2 * (size_t)bb + (size_t)bb * bb + 64;
 }
 
 int panel_grid(int rows, int bb) {

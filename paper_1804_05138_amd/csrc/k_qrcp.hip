@@ -1,17 +1,22 @@
 // Partial QRCP on the sketch (Alg. 1 applied to B(:, i:n) inside Alg. 2).
 //
-// One persistent, co-resident grid.  Every thread owns one sketch column (or
-// one half of it, TPC = 2) in registers for the whole call, so the only
-// global traffic per pivot step is one small candidate record per workgroup
-// and one read of the winning column: each step is
-//   local argmax of the trailing norms -> publish candidate -> grid barrier
-//   -> global argmax (ties: lowest position) -> Householder vector (LAPACK
-//   dlarfg convention) -> apply it to every active column -> exact new norms.
-// The norms are recomputed from the column each step (the definition of r_s
-// in Alg. 1), not downdated, so there is no cancellation to guard against.
+// One persistent, co-resident grid.  Every column of the sketch block lives
+// in registers of TPC threads for the whole call, so the only global traffic
+// per pivot step is one candidate record per workgroup:
+//   1. each workgroup finds its best trailing column (largest norm, ties to
+//      the lowest position) and publishes a record {norm^2, position, slot,
+//      sequence number, column};
+//   2. every workgroup waits until all records carry this step's sequence
+//      number (the global pivot step + 1), which doubles as the grid barrier;
+//   3. every workgroup reads all records, picks the same global winner and
+//      forms the same Householder reflector (LAPACK dlarfg convention) from
+//      the winner's column;
+//   4. every workgroup applies it to its own active columns and recomputes
+//      their trailing norms exactly (the definition of r_s in Alg. 1; no
+//      downdating, so no cancellation to guard against).
 // Columns never move during the call; positions are tracked logically and
-// the columns are written back to their final positions at the end, with
-// the list of moved columns for the matching moves in A.
+// the block is written back in pivot order at the end, together with the
+// list of moved columns for the matching column moves in A.
 #include <limits.h>
 
 #include "internal.h"
@@ -19,58 +24,38 @@
 namespace rq {
 namespace {
 
-RQ_DEV bool better(double n1, int p1, double n2, int p2) {
-  return n1 > n2 || (n1 == n2 && p1 < p2);
-}
-
-RQ_DEV void wave_best(double& n, int& p, int& s) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double n2 = __shfl_xor(n, off, 64);
-    const int p2 = __shfl_xor(p, off, 64);
-    const int s2 = __shfl_xor(s, off, 64);
-    if (better(n2, p2, n, p)) {
-      n = n2;
-      p = p2;
-      s = s2;
-    }
-  }
-}
-
 template <int TPC>
 RQ_DEV double tpc_sum(double v) {
-  if constexpr (TPC == 2) v += __shfl_xor(v, 1, 64);
+  if constexpr (TPC == 2) v = pair_sum_dpp(v);
   return v;
 }
 
-// QT threads per workgroup; every workgroup holds CPW = QT / TPC = 256 columns.
+// QT threads per workgroup; every workgroup holds CPW = QT / TPC = 256 columns,
+// each column split over TPC threads (rows sub, sub + TPC, ...).
 template <int RPT, int TPC, int QT>
 __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
     double* __restrict__ bsk, long long ldb, int l, int nc, int nsteps, int gstep0,
     GridBarrier* bar, double* __restrict__ cand, int cs, int* __restrict__ pairs,
-    int* __restrict__ npairs, int* __restrict__ info) {
+    int* __restrict__ npairs, int* __restrict__ info, int allread) {
   constexpr int CPW = QT / TPC;
+  constexpr int NW = QT / 64;
   const int G = gridDim.x;
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int sub = tid % TPC;
   const int slot = g * CPW + tid / TPC;
   const bool valid = slot < nc;
   bool active = valid;
   int my_pos = slot;
 
-  __shared__ double s_col[RPT * TPC];
-  __shared__ double s_v[RPT * TPC];
   __shared__ int s_p2s[MAX_B];
-  __shared__ double s_wn[QT / 64];
-  __shared__ int s_wp[QT / 64];
-  __shared__ int s_ws[QT / 64];
-  __shared__ double s_bn;
-  __shared__ int s_bp, s_bs;
-  __shared__ double s_beta, s_tau, s_den;
-  __shared__ int s_wslot, s_qslot, s_jpos;
-  __shared__ double s_gn;
-  __shared__ BarrierLocal bl;
+  __shared__ double s_v[MAX_L];  // scaled Householder vector of the step
+  __shared__ double s_wn[NW];
+  __shared__ int s_wp[NW];
+  __shared__ int s_ws[NW];
+  // all G candidate records (allread), or the G headers and the winner's column
+  extern __shared__ double s_rec[];
 
   // A zero sketch pivot in an earlier block: no more pivoting (identity).
   if (*info != 0) {
@@ -79,12 +64,17 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
   }
 
   double x[RPT];
+  {
+    const double* col = bsk + (long long)(valid ? slot : 0) * ldb;
 #pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    const int r = j * TPC + sub;
-    x[j] = (valid && r < l) ? bsk[(long long)slot * ldb + r] : 0.0;
+    for (int j = 0; j < RPT; ++j) {
+      const int r = j * TPC + sub;
+      const double v = col[r < l ? r : 0];
+      x[j] = (valid && r < l) ? v : 0.0;
+    }
   }
   if (tid < nsteps) s_p2s[tid] = tid;
+  if (tid == 0) s_v[MAX_L - 1] = 0.0;
   if (g == 0 && tid == 0) *npairs = 0;
 
   double nrm2 = 0.0;
@@ -93,162 +83,175 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
   nrm2 = tpc_sum<TPC>(nrm2);
 
   for (int t = 0; t < nsteps; ++t) {
-    // ---- (a) best trailing column of this workgroup ----
-    double bn = (active && sub == 0) ? nrm2 : -1.0;
-    int bp = (active && sub == 0) ? my_pos : INT_MAX;
-    int bs = slot;
-    wave_best(bn, bp, bs);
-    if ((tid & 63) == 0) {
-      s_wn[tid >> 6] = bn;
-      s_wp[tid >> 6] = bp;
-      s_ws[tid >> 6] = bs;
+    // ---- (1) best trailing column of this workgroup ----
+    {
+      double bn = (active && sub == 0) ? nrm2 : -1.0;
+      int bp = (active && sub == 0) ? my_pos : INT_MAX;
+      int bs = slot;
+      wave_argmax(bn, bp, bs);
+      if (lane == 0) {
+        s_wn[wave] = bn;
+        s_wp[wave] = bp;
+        s_ws[wave] = bs;
+      }
     }
     __syncthreads();
-    if (tid == 0) {
-      double n = s_wn[0];
-      int p = s_wp[0], s = s_ws[0];
-      for (int w = 1; w < QT / 64; ++w)
-        if (better(s_wn[w], s_wp[w], n, p)) {
-          n = s_wn[w];
-          p = s_wp[w];
-          s = s_ws[w];
-        }
-      s_bn = n;
-      s_bp = p;
-      s_bs = s;
-    }
-    __syncthreads();
+    // slot now at position t (thread 0 last wrote s_p2s before this sync)
+    const int q_at_t = s_p2s[t];
+    double bn = s_wn[0];
+    int bp = s_wp[0], bs = s_ws[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      if (argbetter(s_wn[w], s_wp[w], bn, bp)) {
+        bn = s_wn[w];
+        bp = s_wp[w];
+        bs = s_ws[w];
+      }
 
-    // ---- (b) publish the candidate record ----
+    // ---- publish the candidate record ----
     double* rec = cand + ((long long)(t & 1) * G + g) * cs;
+    const unsigned seq = (unsigned)(gstep0 + t + 1);
     if (tid == 0) {
-      rec[0] = s_bn;
-      rec[1] = (double)s_bp;
-      rec[2] = (double)s_bs;
+      rec[0] = bn;
+      rec[1] = (double)bp;
+      rec[2] = (double)bs;
     }
-    if (valid && active && slot == s_bs) {
+    if (active && slot == bs) {
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const int r = j * TPC + sub;
         if (r < l) rec[4 + r] = x[j];
       }
     }
+    __syncthreads();
+    if (tid == 0) publish_seq(reinterpret_cast<unsigned*>(rec + 3), seq);
 
-    // ---- (c) all candidates are published ----
-    grid_barrier(bar, G, &bl);
+    // ---- (2) wait until every workgroup has published this step ----
+    wait_all_seq(reinterpret_cast<const unsigned*>(cand + (long long)(t & 1) * G * cs + 3),
+                 2LL * cs, G, seq, bar);
 
-    // ---- (d) global winner ----
-    {
-      double wn = -2.0;
-      int wp = INT_MAX, ww = 0;
-      for (int q = tid; q < G; q += QT) {
-        const double* r = cand + ((long long)(t & 1) * G + q) * cs;
-        const double n = r[0];
-        const int p = (n >= 0.0) ? (int)r[1] : INT_MAX;
-        if (better(n, p, wn, wp)) {
-          wn = n;
-          wp = p;
+    // ---- (3) global winner and its reflector, computed by every workgroup ----
+    const double* recs = cand + (long long)(t & 1) * G * cs;
+    const double* wcol;  // the winner's column (rows 0..l-1)
+    double gn;
+    int jpos, wslot;
+    if (allread) {
+      // one read of every record into LDS, all loads in flight together
+      const int total = G * cs;
+      constexpr int NL = 8192 / QT;
+      double v[NL];
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int e = tid + u * QT;
+        v[u] = recs[e < total ? e : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int e = tid + u * QT;
+        if (e < total) s_rec[e] = v[u];
+      }
+      __syncthreads();
+      // each wave scans the headers (lane q, q + 64, ...) and reduces with DPP
+      gn = -2.0;
+      jpos = INT_MAX;
+      int ww = 0;
+      for (int q = lane; q < G; q += 64) {
+        const double n = s_rec[q * cs];
+        const int p = (n >= 0.0) ? (int)s_rec[q * cs + 1] : INT_MAX;
+        if (argbetter(n, p, gn, jpos)) {
+          gn = n;
+          jpos = p;
           ww = q;
         }
       }
-      wave_best(wn, wp, ww);
-      if ((tid & 63) == 0) {
-        s_wn[tid >> 6] = wn;
-        s_wp[tid >> 6] = wp;
-        s_ws[tid >> 6] = ww;
-      }
+      wave_argmax(gn, jpos, ww);
+      wcol = s_rec + ww * cs + 4;
+      wslot = (int)s_rec[ww * cs + 2];
+    } else {
+      // headers first, then the winner's column
+      for (int e = tid; e < G * 4; e += QT) s_rec[e] = recs[(e >> 2) * cs + (e & 3)];
       __syncthreads();
-      if (tid == 0) {
-        double n = s_wn[0];
-        int p = s_wp[0], w = s_ws[0];
-        for (int k = 1; k < QT / 64; ++k)
-          if (better(s_wn[k], s_wp[k], n, p)) {
-            n = s_wn[k];
-            p = s_wp[k];
-            w = s_ws[k];
-          }
-        s_gn = n;
-        s_jpos = p;
-        s_wslot = (int)cand[((long long)(t & 1) * G + w) * cs + 2];
-        s_ws[0] = w;
-      }
-      __syncthreads();
-    }
-    const int wwg = s_ws[0];
-    const double* wrec = cand + ((long long)(t & 1) * G + wwg) * cs;
-    for (int r = tid; r < l; r += QT) s_col[r] = (r >= t) ? wrec[4 + r] : 0.0;
-    __syncthreads();
-
-    // ---- (e) Householder reflector of the winning column (dlarfg) ----
-    if (tid < 64) {
-      double acc = 0.0;
-      for (int r = t + 1 + tid; r < l; r += 64) acc += s_col[r] * s_col[r];
-      acc = wave_sum(acc);
-      if (tid == 0) {
-        const double alpha = s_col[t];
-        double beta = alpha, tau = 0.0, den = 1.0;
-        if (acc > 0.0) {
-          const double nrm = hypot(alpha, sqrt(acc));
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-          den = alpha - beta;
+      gn = -2.0;
+      jpos = INT_MAX;
+      int ww = 0;
+      for (int q = lane; q < G; q += 64) {
+        const double n = s_rec[q * 4];
+        const int p = (n >= 0.0) ? (int)s_rec[q * 4 + 1] : INT_MAX;
+        if (argbetter(n, p, gn, jpos)) {
+          gn = n;
+          jpos = p;
+          ww = q;
         }
-        s_beta = beta;
-        s_tau = tau;
-        s_den = den;
-        const int q = s_p2s[t];
-        s_qslot = q;
-        s_p2s[t] = s_wslot;
-        if (s_jpos < nsteps && s_jpos != t) s_p2s[s_jpos] = q;
-        if (g == 0 && s_gn == 0.0 && *info == 0) *info = gstep0 + t + 1;
       }
+      wave_argmax(gn, jpos, ww);
+      wslot = (int)s_rec[ww * 4 + 2];
+      double* colbuf = s_rec + G * 4;
+      for (int r = tid; r < l; r += QT) colbuf[r] = recs[(long long)ww * cs + 4 + r];
+      __syncthreads();
+      wcol = colbuf;
+    }
+    // dlarfg on the winner's rows t..l-1 (every wave, same order, same result)
+    double xn2 = 0.0;
+    for (int r = t + 1 + lane; r < l; r += 64) xn2 += wcol[r] * wcol[r];
+    xn2 = wave_sum_dpp(xn2);
+    const double alpha = wcol[t];
+    double beta = alpha, tau = 0.0, den = 1.0;
+    if (xn2 > 0.0) {
+      const double nrm = hypot(alpha, sqrt(xn2));
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      den = alpha - beta;
+    }
+    if (g == 0 && tid == 0 && gn == 0.0 && *info == 0) *info = gstep0 + t + 1;
+    // v_t = 1, v_r = wcol[r] / (alpha - beta) for r > t, zero above t
+    {
+      const double inv = 1.0 / den;
+      for (int r = tid; r < l; r += QT)
+        s_v[r] = (r == t) ? 1.0 : ((r > t && tau != 0.0) ? wcol[r] * inv : 0.0);
     }
     __syncthreads();
-    for (int r = tid; r < l; r += QT)
-      s_v[r] = (r == t) ? 1.0 : ((r > t && s_tau != 0.0) ? s_col[r] / s_den : 0.0);
-    __syncthreads();
 
-    const double beta = s_beta, tau = s_tau;
-    const int wsl = s_wslot, qsl = s_qslot, jpos = s_jpos;
-
-    // ---- (f) bookkeeping of positions ----
+    // ---- position bookkeeping (identical in every workgroup) ----
+    if (tid == 0) {
+      s_p2s[t] = wslot;
+      if (jpos < nsteps && jpos != t) s_p2s[jpos] = q_at_t;
+    }
     if (valid) {
-      if (slot == wsl) {
+      if (slot == wslot) {
         my_pos = t;
         active = false;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           const int r = j * TPC + sub;
-          if (r == t) x[j] = beta;
-          else if (r > t) x[j] = 0.0;
+          x[j] = (r == t) ? beta : ((r > t) ? 0.0 : x[j]);
         }
-      } else if (slot == qsl) {
+      } else if (slot == q_at_t) {
         my_pos = jpos;
       }
     }
 
-    // ---- (g) apply H to the active columns, new trailing norms ----
+    // ---- (4) apply H = I - tau v v^T to the active columns, new norms ----
     if (active) {
       if (tau != 0.0) {
         double d = 0.0;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           const int r = j * TPC + sub;
-          if (r >= t && r < l) d += s_v[r] * x[j];
+          d += s_v[r < l ? r : MAX_L - 1] * x[j];  // rows past l hold x = 0
         }
         d = tpc_sum<TPC>(d);
         const double f = tau * d;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           const int r = j * TPC + sub;
-          if (r >= t && r < l) x[j] -= f * s_v[r];
+          x[j] -= f * s_v[r < l ? r : MAX_L - 1];
         }
       }
       double nn = 0.0;
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const int r = j * TPC + sub;
-        if (r > t && r < l) nn += x[j] * x[j];
+        nn += (r > t) ? x[j] * x[j] : 0.0;
       }
       nrm2 = tpc_sum<TPC>(nn);
     }
@@ -280,12 +283,18 @@ int launch_t(hipStream_t s, double* b, long long ldb, int l, int nc, int nsteps,
   int dev = 0, ncu = 0, per_cu = 0;
   RQ_HIP_CHECK(hipGetDevice(&dev));
   RQ_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  // read all candidate records in one go when they fit in 64 KB of LDS
+  const size_t rec_bytes = (size_t)G * cs * sizeof(double);
+  const int allread = rec_bytes <= 64 * 1024 ? 1 : 0;
+  const size_t shmem = allread ? rec_bytes : ((size_t)G * 4 + cs) * sizeof(double);
+  RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   RQ_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(kern), QT, 0));
-  // the grid barrier needs every workgroup resident at once
+      &per_cu, reinterpret_cast<const void*>(kern), QT, shmem));
+  // the exchange waits on every workgroup: all must be resident at once
   if (G > ncu * per_cu) return RQ_ERR_LIMIT;
-  hipLaunchKernelGGL(kern, dim3(G), dim3(QT), 0, s, b, ldb, l, nc, nsteps, gstep0, &scr->bar, cand,
-                     cs, pairs, &scr->npairs, info);
+  hipLaunchKernelGGL(kern, dim3(G), dim3(QT), shmem, s, b, ldb, l, nc, nsteps, gstep0, &scr->bar,
+                     cand, cs, pairs, &scr->npairs, info, allread);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
@@ -293,15 +302,14 @@ int launch_t(hipStream_t s, double* b, long long ldb, int l, int nc, int nsteps,
 }  // namespace
 
 size_t qrcp_cand_doubles(int l, int nc) {
-  const int cpw = 256;
-  const size_t G = (size_t)(nc + cpw - 1) / cpw;
+  const size_t G = (size_t)(nc + 255) / 256;
   const size_t cs = ((l + 4) + 7) / 8 * 8;
   return 2 * G * cs;
 }
 
 int qrcp_sketch_grid(int l, int nc) {
-  const int cpw = 256;
-  return (nc + cpw - 1) / cpw;
+  (void)l;
+  return (nc + 255) / 256;
 }
 
 int launch_qrcp_sketch(hipStream_t s, double* b, long long ldb, int l, int c0, int nc, int nsteps,

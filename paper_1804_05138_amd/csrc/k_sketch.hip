@@ -53,20 +53,34 @@ __global__ __launch_bounds__(GT, 2) void k_sketch_f64(int m, int n, int l,
   v4d acc[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) acc[mb] = v4d{0.0, 0.0, 0.0, 0.0};
-  const double* acol = a + (long long)col * lda;
+  // Loads are unconditional from clamped (valid) addresses and masked
+  // afterwards, so they are all in flight together.
+  const double* acol = a + (long long)(colok ? col : 0) * lda;
 
   for (int kt = k0; kt < k1; kt += KT) {
     // stage Omega(0:l, kt:kt+KT) as [k][row]
-    for (int e = tid; e < KT * MB * 16; e += GT) {
+    constexpr int NS = (KT * MB * 16 + GT - 1) / GT;
+    double ov[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + u * GT;
       const int r = e % (MB * 16), kk = e / (MB * 16);
       const int k = kt + kk;
-      sO[kk * LDS_L + r] = (r < l && k < k1) ? om[(long long)k * ldo + r] : 0.0;
+      ov[u] = om[(long long)(k < k1 ? k : k1 - 1) * ldo + (r < l ? r : 0)];
     }
+    // rows k >= k1 of this tile meet zero Omega columns, so clamped reads of A
+    // need no mask; columns past n are never stored
     double bv[KT / 4];
 #pragma unroll
     for (int kq = 0; kq < KT / 4; ++kq) {
       const int k = kt + 4 * kq + lg;
-      bv[kq] = (colok && k < k1) ? acol[k] : 0.0;
+      bv[kq] = acol[k < k1 ? k : k1 - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + u * GT;
+      const int r = e % (MB * 16), kk = e / (MB * 16);
+      if (e < KT * MB * 16) sO[kk * LDS_L + r] = (r < l && kt + kk < k1) ? ov[u] : 0.0;
     }
     __syncthreads();
 #pragma unroll

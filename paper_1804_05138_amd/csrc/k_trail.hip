@@ -53,43 +53,47 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
   const int ri1 = min(m, ri0 + rows_per_split);
   const int in = i + bbu;  // first row of the next reflectors
 
+  // Loads below are unconditional from clamped (always valid) addresses and
+  // masked afterwards: a load under a branch costs a full memory round trip.
+  const int cols = colok ? col : c_begin;  // a valid column for masked lanes
   double bw[BBM / 4];
 #pragma unroll
   for (int kq = 0; kq < BBM / 4; ++kq) {
     const int q = 4 * kq + lg;
-    bw[kq] = (colok && q < bbu) ? -wp[(long long)(col - w0) * ldw + q] : 0.0;
+    const double v = (bbu > 0) ? wp[(long long)(cols - w0) * ldw + (q < bbu ? q : 0)] : 0.0;
+    bw[kq] = (colok && q < bbu) ? -v : 0.0;
   }
   v4d acc[BBM / 16];
 #pragma unroll
   for (int qb = 0; qb < BBM / 16; ++qb) acc[qb] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  double* acol = a + (long long)col * lda;
+  double* acol = a + (long long)cols * lda;
   // this thread's share of a tile's reflector rows: row rr, columns q0 + QS*j
   const int rr = tid % TR, q0 = tid / TR;
   double pu[NQ], pn[NQ];
+  // raw values only; the unit-lower-trapezoidal mask is applied when staging
   auto fetch_v = [&](int r0) {
     const int r = r0 + rr;
+    const int rsafe = r < m ? r : m - 1;
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
       const int q = q0 + QS * j;
-      double vu = 0.0, vn = 0.0;
-      if (r < m) {
-        const int du = r - i, dv = r - in;
-        if (q < bbu) vu = (du > q) ? a[(long long)(i + q) * lda + r] : (du == q ? 1.0 : 0.0);
-        if (q < bbn) vn = (dv > q) ? a[(long long)(in + q) * lda + r] : (dv == q ? 1.0 : 0.0);
-      }
-      pu[j] = vu;
-      pn[j] = vn;
+      pu[j] = a[(long long)(i + (q < bbu ? q : 0)) * lda + rsafe];
+      pn[j] = a[(long long)(q < bbn ? in + q : i) * lda + rsafe];
     }
   };
-  // this wave's 16 columns of a tile, in accumulator layout
+  // This wave's 16 columns of a tile, in accumulator layout.  Row splits are
+  // multiples of the tile height, so rows past ri1 only occur past m, where
+  // the staged reflector rows are zero; those rows (clamped to m-1) and the
+  // columns past c_end (clamped to c_begin) only feed results that are never
+  // stored, so no masking is needed.
   auto fetch_a = [&](int r0, v4d* dd) {
 #pragma unroll
     for (int b = 0; b < TR / 16; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = r0 + 16 * b + acc_row<double>(lg, e);
-        dd[b][e] = (colok && row < ri1) ? acol[row] : 0.0;
+        dd[b][e] = acol[row < m ? row : m - 1];
       }
   };
 
@@ -98,11 +102,24 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
   fetch_a(ri0, d);
   for (int r0 = ri0; r0 < ri1; r0 += TR) {
     // ---- stage this tile's reflector rows (fetched one tile ahead) ----
+    {
+      // flat selects (no branches): zero outside the block width and past row m,
+      // so partial blocks run the full-width MFMA loop on zero padding
+      const int r = r0 + rr;
+      const int du = r - i, dv = r - in;
+      const bool rin = r < m;
 #pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      const int q = q0 + QS * j;
-      sVuT[q * TR + (rr ^ ((q & 1) << 4))] = pu[j];
-      sVn[rr * BBM + (q ^ swz_n(rr))] = pn[j];
+      for (int j = 0; j < NQ; ++j) {
+        const int q = q0 + QS * j;
+        double vu = (du == q) ? 1.0 : 0.0;
+        vu = (du > q) ? pu[j] : vu;
+        vu = (rin & (q < bbu)) ? vu : 0.0;
+        double vn = (dv == q) ? 1.0 : 0.0;
+        vn = (dv > q) ? pn[j] : vn;
+        vn = (rin & (q < bbn)) ? vn : 0.0;
+        sVuT[q * TR + (rr ^ ((q & 1) << 4))] = vu;
+        sVn[rr * BBM + (q ^ swz_n(rr))] = vn;
+      }
     }
     __syncthreads();
     // ---- fetch the next tile while this one is on the MFMAs ----
@@ -115,13 +132,11 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
     if (bbu > 0) {
 #pragma unroll
       for (int kq = 0; kq < BBM / 4; ++kq) {
-        if (4 * kq < bbu) {
-          const int q = 4 * kq + lg;
+        const int q = 4 * kq + lg;
 #pragma unroll
-          for (int b = 0; b < TR / 16; ++b) {
-            const double av = sVuT[q * TR + ((16 * b + lr16) ^ ((q & 1) << 4))];
-            d[b] = mfma_f64(av, bw[kq], d[b]);
-          }
+        for (int b = 0; b < TR / 16; ++b) {
+          const double av = sVuT[q * TR + ((16 * b + lr16) ^ ((q & 1) << 4))];
+          d[b] = mfma_f64(av, bw[kq], d[b]);
         }
       }
 #pragma unroll
@@ -129,7 +144,7 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = r0 + 16 * b + acc_row<double>(lg, e);
-          if (colok && row < ri1) acol[row] = d[b][e];
+          if (colok & (row < ri1)) acol[row] = d[b][e];
         }
     }
     if (bbn > 0) {
@@ -140,10 +155,8 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
           const int r = 16 * b + acc_row<double>(lg, e);
 #pragma unroll
           for (int qb = 0; qb < BBM / 16; ++qb) {
-            if (16 * qb < bbn) {
-              const double av = sVn[r * BBM + ((16 * qb + lr16) ^ swz_n(r))];
-              acc[qb] = mfma_f64(av, d[b][e], acc[qb]);
-            }
+            const double av = sVn[r * BBM + ((16 * qb + lr16) ^ swz_n(r))];
+            acc[qb] = mfma_f64(av, d[b][e], acc[qb]);
           }
         }
     }

@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--matrix", choices=("lowrank", "gaussian"), default="lowrank",
                     help="gaussian: i.i.d. N(0,1) A of the same size (no QR in the generator; "
                          "for profiler runs, where kernel times depend only on the sizes)")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after the timed steps, run one plain elementwise copy of this many MiB "
+                         "(FP64), whose HBM counters calibrate the trailing update's")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
@@ -141,6 +144,16 @@ def main():
     jp = jpvt.cpu()
     assert int(info.item()) == 0
     assert torch.equal(torch.sort(jp.long()).values, torch.arange(N))
+
+    if args.calibration_copy_mib > 0:
+        nel = args.calibration_copy_mib * (1 << 20) // 8
+        src = torch.randn(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)   # reads and writes nel * 8 bytes
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
+        del src, dst
 
     ms_step = (t2 - t1) / args.steps * 1e3
     flops = rqrcp_flops(M, N, K, B, P)

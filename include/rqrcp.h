@@ -126,6 +126,38 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, d
 int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, const double *A, int lda, const double *tau,
                  double *Q, int ldq, void *ws, size_t ws_bytes);
 
+/* ---- Spectrum-revealing swaps (Alg. 3, Section IV) ---- */
+#define SRQR_EXACT 1u /* g2 from the exact row norms of Rhat^-1 instead of d Gaussian probes */
+
+/* Workspace in bytes (host output) for srqr_swap with these sizes. */
+int srqr_workspace_size(int m, int n, int l, const rqrcp_params *prm, int d, unsigned sflags,
+                        size_t *bytes);
+
+/* Alg. 3 after an l-step rqrcp_factor (k = l) with the same prm, 1 <= l < min(m, n).
+ *  g          tolerance g > 1 of the g2 test (Section IV-C: g2 = |alpha| ||Rhat^-T||_{1,2}).
+ *  d          probe count of the g2 estimate g2 ~ |alpha| ||Omega Rhat^-T||_{1,2} / sqrt(d),
+ *             Omega (d x (l+1)) from Philox(prm->seed, stream 2^32 + j) at estimate j
+ *             (ignored with SRQR_EXACT).
+ *  max_swaps  cap on the round-robin swaps (< 0: 2n).
+ *  A0         (in) the original m x n matrix (lda0), used to recompute the
+ *             factorization after swaps.
+ *  A, jpvt, tau (in/out) the factorization from rqrcp_factor (tau has room for
+ *             l+1 entries); on exit an (l+1)-step factorization in the same
+ *             storage: one more Householder step if no swap was needed, else the
+ *             frozen-pivot factorization of A0(:, jpvt) with the final pivots
+ *             (Givens rotations cannot be represented by V/tau).
+ *  B          (in) the final sketch from rqrcp_factor (its columns l..n-1 give the
+ *             initial estimates r_i = ||B(:, i)||^2 / (b+p)).
+ *  g2_out     (out, device, may be NULL) the last g2 value.
+ *  nswaps_out (out, device, may be NULL) the number of swaps.
+ *  info       (out, device) 0, or -max_swaps if the cap was reached with g2 > g.
+ * Synchronizes the stream once per g2 evaluation (the loop is host-driven).
+ * Limits: l + 1 <= 4096. */
+int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params *prm, double g, int d,
+              int max_swaps, unsigned sflags, const double *A0, int lda0, double *A, int lda,
+              int32_t *jpvt, double *tau, const double *B, int ldb, double *g2_out,
+              int32_t *nswaps_out, int32_t *info, void *ws, size_t ws_bytes);
+
 /* Synchronizes the handle's stream and returns RQRCP_ERR_BARRIER if a
  * persistent kernel reported a barrier timeout since the last check (and
  * clears the flag), RQRCP_ERR_HIP on a HIP error, else 0.  `ws` is the

@@ -22,6 +22,7 @@ F64 = 0
 F32 = 1
 FROZEN_PIVOTS = 1
 USER_SKETCH = 2
+SRQR_EXACT = 1
 
 STATUS = {
     1001: "HIP runtime error", 1002: "workspace too small",
@@ -34,6 +35,7 @@ EXPORTS = (
     "rqrcp_create", "rqrcp_destroy", "rqrcp_set_stream", "rqrcp_workspace_size",
     "rqrcp_limits", "rqrcp_gaussian", "rqrcp_sketch", "rqrcp_factor", "rqrcp_form_q",
     "rqrcp_check", "rqrcp_status_string", "rqrcp_set_timing", "rqrcp_read_timing",
+    "srqr_workspace_size", "srqr_swap",
 )
 PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other")
 
@@ -67,6 +69,9 @@ def load_library(path: str = LIB_PATH):
         "rqrcp_factor": (i, [vp, i, i, i, P(Params), vp, i, vp, vp, vp, i, vp, vp, sz]),
         "rqrcp_form_q": (i, [vp, i, i, i, vp, i, vp, vp, i, vp, sz]),
         "rqrcp_check": (i, [vp, vp]),
+        "srqr_workspace_size": (i, [i, i, i, P(Params), i, ctypes.c_uint, P(sz)]),
+        "srqr_swap": (i, [vp, i, i, i, P(Params), ctypes.c_double, i, i, ctypes.c_uint,
+                          vp, i, vp, i, vp, vp, vp, i, vp, vp, vp, vp, sz]),
         "rqrcp_status_string": (ctypes.c_char_p, [i]),
         "rqrcp_set_timing": (i, [vp, i]),
         "rqrcp_read_timing": (i, [vp, P(ctypes.c_double), P(i), P(ctypes.c_double),
@@ -277,6 +282,47 @@ def form_q(fact_a, tau, k=None, b=64, ws=None):
                                         _ptr(q), max(1, m), _ptr(ws), ws.numel()),
            "rqrcp_form_q")
     return q
+
+
+@dataclass
+class SRQR:
+    a: object       # m x n: the (l+1)-step factorization (LAPACK storage)
+    jpvt: object    # int32 (n,)
+    tau: object     # float64 (l+1,)
+    g2: object      # float64 (1,): last g2 value
+    nswaps: object  # int32 (1,)
+    info: object    # int32 (1,): 0, or -max_swaps if the cap was reached
+
+
+def srqr(a0, l, b, p, g, seed=0, *, d=16, exact=False, max_swaps=-1, sketch_b=None):
+    """Alg. 3: the l-step RQRCP of ``a0`` followed by spectrum-revealing swaps.
+
+    sketch_b: a precomputed sketch (e.g. Omega = I) for the RQRCP start.
+    Returns an SRQR with device tensors (synchronizes once per g2 evaluation).
+    """
+    torch = _torch()
+    a0 = colmajor(a0, torch.float64)
+    m, n = a0.shape
+    dev = a0.device
+    f = factor(a0, l, b, p, seed, sketch_b=sketch_b)
+    tau = torch.zeros(l + 1, dtype=torch.float64, device=dev)
+    tau[:l].copy_(f.tau)
+    g2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    ns = torch.zeros(1, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    flags = SRQR_EXACT if exact else 0
+    prm = Params(b, p, seed, F64, 0)
+    lib = load_library()
+    nb = ctypes.c_size_t()
+    _check(lib.srqr_workspace_size(m, n, l, ctypes.byref(prm), d, flags, ctypes.byref(nb)),
+           "srqr_workspace_size")
+    ws = workspace(nb.value, dev)
+    _check(lib.srqr_swap(handle(), m, n, l, ctypes.byref(prm), float(g), d, max_swaps, flags,
+                         _ptr(a0), _ld(a0), _ptr(f.a), _ld(f.a), _ptr(f.jpvt), _ptr(tau),
+                         _ptr(f.b), _ld(f.b), _ptr(g2), _ptr(ns), _ptr(info), _ptr(ws),
+                         ws.numel()), "srqr_swap")
+    _check(lib.rqrcp_check(handle(), _ptr(ws)), "rqrcp_check")
+    return SRQR(f.a, f.jpvt, tau, g2, ns, info)
 
 
 def set_timing(enable: bool):

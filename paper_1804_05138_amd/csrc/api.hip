@@ -24,6 +24,7 @@
 #include "../../include/rqrcp.h"
 #include "gemm.h"
 #include "internal.h"
+#include "srqr.h"
 
 struct rqrcp_ctx {
   hipStream_t stream;
@@ -179,6 +180,8 @@ __global__ void k_copy_cols(int m, int n, const double* __restrict__ src, long l
     dst[c * ldd + r] = src[sc * lds + r];
   }
 }
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
 
 unsigned grid_for(long long total) {
   long long g = (total + 255) / 256;
@@ -437,6 +440,112 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, d
       break;
     }
   }
+  return 0;
+}
+
+int srqr_workspace_size(int m, int n, int l, const rqrcp_params* prm, int d, unsigned sflags,
+                        size_t* bytes) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (l < 1 || l >= std::min(m, n)) return -3;
+  if (!valid_params(prm)) return -4;
+  if (d < 1 && !(sflags & SRQR_EXACT)) return -5;
+  if (!bytes) return -7;
+  const size_t fac = align_up(layout(m, n, l + 1, prm->b, prm->p, RQRCP_FROZEN_PIVOTS).total);
+  *bytes = fac + srqr_layout(m, n, l, d, (sflags & SRQR_EXACT) ? 1 : 0).total;
+  return 0;
+}
+
+int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params* prm, double g, int d,
+              int max_swaps, unsigned sflags, const double* A0, int lda0, double* A, int lda,
+              int32_t* jpvt, double* tau, const double* B, int ldb, double* g2_out,
+              int32_t* nswaps_out, int32_t* info, void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (l < 1 || l >= std::min(m, n)) return -4;
+  if (!valid_params(prm) || prm->b > MAX_B) return -5;
+  if (!(g > 1.0)) return -6;
+  const int exact = (sflags & SRQR_EXACT) ? 1 : 0;
+  if (!exact && d < 1) return -7;
+  if (!A0) return -10;
+  if (lda0 < m) return -11;
+  if (!A) return -12;
+  if (lda < m) return -13;
+  if (!jpvt) return -14;
+  if (!tau) return -15;
+  if (!B) return -16;
+  if (ldb < prm->b + prm->p) return -17;
+  if (!info) return -20;
+  if (l + 1 > 4096) return RQRCP_ERR_LIMIT;
+  size_t need = 0;
+  int rc = srqr_workspace_size(m, n, l, prm, d, sflags, &need);
+  if (rc) return rc;
+  if (!ws || ws_bytes < need) return RQRCP_ERR_WORKSPACE;
+  if (max_swaps < 0) max_swaps = 2 * n;
+  hipStream_t s = h->stream;
+  const size_t fac = align_up(layout(m, n, l + 1, prm->b, prm->p, RQRCP_FROZEN_PIVOTS).total);
+  char* sw = (char*)ws + fac;
+  const SrqrLayout L = srqr_layout(m, n, l, d, exact);
+  double* est = (double*)(sw + L.est);
+  double* om = (double*)(sw + L.omega);
+  double* sc = (double*)(sw + L.sc);
+  const int deff = exact ? l + 1 : d;
+  // the scratch words rqrcp_check reads start cleared, whether or not a
+  // refactorization runs
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, (QrcpScratch*)((char*)ws + QSCR_OFF),
+                     (PanelScratch*)((char*)ws + PSCR_OFF), info, nullptr, 0, 0, nullptr, 0LL);
+  RQ_HIP_CHECK(hipGetLastError());
+
+  auto g2_round = [&](int it) -> int {
+    if (!exact) {
+      int r = launch_gaussian(s, d, l + 1, prm->seed, (1ull << 32) + (uint64_t)it, om, d);
+      if (r) return r;
+    }
+    return launch_srqr_g2(s, l, A, lda, om, deff, exact, L, sw, g2_out);
+  };
+  auto read_g2 = [&](double* v) -> int {
+    if (hipMemcpyAsync(v, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return RQRCP_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RQRCP_ERR_HIP;
+    return 0;
+  };
+
+  // r_i from the final sketch, the first pick, one QR step, g2
+  rc = launch_srqr_init(s, m, n, l, prm->b + prm->p, A, lda, jpvt, B, ldb, est);
+  if (rc) return rc;
+  rc = launch_srqr_pick_qr(s, m, n, l, A, lda, jpvt, est, tau, sc);
+  if (rc) return rc;
+  rc = g2_round(0);
+  if (rc) return rc;
+  double g2 = 0.0;
+  rc = read_g2(&g2);
+  if (rc) return rc;
+  int nswaps = 0;
+  while (g2 > g && nswaps < max_swaps) {
+    rc = launch_srqr_rotate(s, m, n, l, A, lda, jpvt, L, sw);
+    if (rc) return rc;
+    rc = launch_srqr_pick_qr(s, m, n, l, A, lda, jpvt, est, tau, sc);
+    if (rc) return rc;
+    ++nswaps;
+    rc = g2_round(nswaps);
+    if (rc) return rc;
+    rc = read_g2(&g2);
+    if (rc) return rc;
+  }
+  if (nswaps > 0) {
+    // Givens rotations are not representable by (V, tau): refactor A0(:, jpvt)
+    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n, A0,
+                       (long long)lda0, A, (long long)lda, (const int*)nullptr);
+    RQ_HIP_CHECK(hipGetLastError());
+    rqrcp_params fp = *prm;
+    fp.flags = RQRCP_FROZEN_PIVOTS;
+    rc = rqrcp_factor(h, m, n, l + 1, &fp, A, lda, jpvt, tau, nullptr, 0, info, ws, fac);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, info, (g2 > g) ? -max_swaps : 0);
+  if (nswaps_out) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, nswaps_out, nswaps);
+  RQ_HIP_CHECK(hipGetLastError());
   return 0;
 }
 

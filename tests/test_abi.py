@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1804_05138_amd", "librqrcp.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rqrcp_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:rqrcp|srqr)_[a-z_]+)\s*\(", text)))
 
 
 def test_header_declares_the_entry_points():
@@ -53,6 +53,13 @@ def test_argument_checks_without_gpu():
     assert lib.rqrcp_workspace_size(100, 80, 20, ctypes.byref(bad), ctypes.byref(out)) == -4
     assert lib.rqrcp_factor(None, 10, 10, 5, ctypes.byref(prm), None, 10, None, None, None, 40,
                             None, None, 0) == -1
+    sw = ctypes.c_size_t()
+    assert lib.srqr_workspace_size(100, 80, 20, ctypes.byref(prm), 16, 0, ctypes.byref(sw)) == 0
+    assert sw.value > 0
+    assert lib.srqr_workspace_size(100, 80, 80, ctypes.byref(prm), 16, 0, ctypes.byref(sw)) == -3
+    assert lib.srqr_workspace_size(100, 80, 20, ctypes.byref(prm), 0, 0, ctypes.byref(sw)) == -5
+    assert lib.srqr_workspace_size(100, 80, 20, ctypes.byref(prm), 0, rq.SRQR_EXACT,
+                                   ctypes.byref(sw)) == 0
     assert lib.rqrcp_status_string(1002) == b"workspace too small"
     assert lib.rqrcp_status_string(-3) == b"invalid argument"
 

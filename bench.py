@@ -185,7 +185,7 @@ def main():
         "pct_fp64_mfma_peak": round(100.0 * tflops / PEAK_FP64_MFMA, 2),
         "phases_ms_per_step": {ph: round(v[0] / args.steps, 3) for ph, v in phases.items() if v[1]},
         "roofline": {
-            "kernel": "k_trail_f64 (fused trailing update)",
+            "kernel": "k_trail<double, 64> (fused trailing update)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
             "peak": PEAK_FP64_MFMA,

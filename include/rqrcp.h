@@ -56,20 +56,28 @@ typedef struct rqrcp_ctx *rqrcp_handle;
 #define RQRCP_ERR_LIMIT 1005       /* size beyond what the kernels accept (see rqrcp_limits) */
 #define RQRCP_ERR_BARRIER 1006     /* a persistent kernel's grid barrier timed out */
 
-/* Element types. */
+/* Element types.  A may be FP64 or FP32; the sketch B, Omega, tau and all
+ * reflector arithmetic are FP64.  The sketch product may run in FP64, BF16 or
+ * FP8 (OCP e4m3); with an FP32 A the trailing update runs on FP32 MFMA (the
+ * mixed-precision form; the paper itself computes everything in FP64). */
 #define RQRCP_F64 0
 #define RQRCP_F32 1
+#define RQRCP_BF16 2
+#define RQRCP_F8E4M3 3
 
 /* rqrcp_params.flags */
 #define RQRCP_FROZEN_PIVOTS 1u /* jpvt is an input: factor A(:, jpvt) without pivoting */
 #define RQRCP_USER_SKETCH 2u   /* B already holds the sketch Omega A (e.g. from rqrcp_sketch) */
 
 typedef struct {
-  int b;          /* block size, 1 <= b <= 128 (Alg. 2 "block size b") */
-  int p;          /* oversampling, p >= 0, b + p <= 160 (Alg. 2 "oversampling size p") */
-  uint64_t seed;  /* Philox key word 0 of Omega (key word 1 = stream 0) */
-  int a_type;     /* RQRCP_F64 (only type of this version) */
-  unsigned flags; /* RQRCP_FROZEN_PIVOTS | RQRCP_USER_SKETCH */
+  int b;           /* block size, 1 <= b <= 128 (Alg. 2 "block size b") */
+  int p;           /* oversampling, p >= 0, b + p <= 160 (Alg. 2 "oversampling size p") */
+  uint64_t seed;   /* Philox key word 0 of Omega (key word 1 = stream 0) */
+  int a_type;      /* storage of A: RQRCP_F64, or RQRCP_F32 (then the trailing update
+                      runs in FP32 and R, V are stored in FP32) */
+  int sketch_type; /* arithmetic of B = Omega A: RQRCP_F64, RQRCP_BF16 or RQRCP_F8E4M3
+                      (FP32 accumulation; FP8 with per-column power-of-two scales) */
+  unsigned flags;  /* RQRCP_FROZEN_PIVOTS | RQRCP_USER_SKETCH */
 } rqrcp_params;
 
 /* Create a handle bound to `stream` (a hipStream_t; NULL = default stream)
@@ -98,14 +106,19 @@ int rqrcp_limits(int l, int *max_b, int *max_l, int *max_n);
 int rqrcp_gaussian(rqrcp_handle h, int rows, int cols, uint64_t seed, uint64_t stream,
                    double *out, int ld);
 
-/* Sketch B = Omega A (Alg. 2, "Compute B = Omega A"); A is m x n FP64 (lda),
- * B is l x n FP64 (ldb).  Omega: l x m FP64 (ldo) supplied by the caller, or
- * NULL to draw it from Philox(seed, stream 0) into the workspace. */
-int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, const double *A, int lda,
-                 const double *Omega, int ldo, double *B, int ldb, void *ws, size_t ws_bytes);
+/* Sketch B = Omega A (Alg. 2, "Compute B = Omega A"); A is m x n (lda) of
+ * a_type (RQRCP_F64 or RQRCP_F32), B is l x n FP64 (ldb).  sketch_type is the
+ * product's arithmetic (RQRCP_F64, RQRCP_BF16 or RQRCP_F8E4M3; see
+ * rqrcp_params).  Omega: l x m FP64 (ldo) supplied by the caller, or NULL to
+ * draw it from Philox(seed, stream 0) into the workspace.  Workspace: that of
+ * rqrcp_factor with the same m, n, b + p = l and sketch_type. */
+int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, int a_type, const void *A,
+                 int lda, int sketch_type, const double *Omega, int ldo, double *B, int ldb,
+                 void *ws, size_t ws_bytes);
 
 /* Truncated RQRCP (Alg. 2) of the m x n matrix A to rank k, 1 <= k <= min(m, n).
- *  A     (in/out) m x n, lda: the factorization in LAPACK storage (see top).
+ *  A     (in/out) m x n, lda, of prm->a_type: the factorization in LAPACK
+ *        storage (see top).
  *  jpvt  (out) n ints; with RQRCP_FROZEN_PIVOTS an input permutation.
  *  tau   (out) k doubles.
  *  B     (in/out) (b+p) x n sketch, ldb >= b+p.  Computed from Philox(seed)
@@ -117,14 +130,15 @@ int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, const doubl
  *        updated and the remaining steps take the columns in their current
  *        order; the factorization itself is completed).
  * Pivot ties go to the lowest current position. */
-int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, double *A, int lda,
+int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, void *A, int lda,
                  int32_t *jpvt, double *tau, double *B, int ldb, int32_t *info, void *ws,
                  size_t ws_bytes);
 
 /* Explicit Q1 = H_0 ... H_{k-1} [I_k; 0] (m x k, ldq) from a factorization
- * (A, lda, tau); b is the block size used to apply the reflectors. */
-int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, const double *A, int lda, const double *tau,
-                 double *Q, int ldq, void *ws, size_t ws_bytes);
+ * (A, lda, tau); b is the block size used to apply the reflectors; A and Q
+ * are of a_type (RQRCP_F64 or RQRCP_F32; FP32 products on FP32 MFMA). */
+int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, int a_type, const void *A, int lda,
+                 const double *tau, void *Q, int ldq, void *ws, size_t ws_bytes);
 
 /* ---- Spectrum-revealing swaps (Alg. 3, Section IV) ---- */
 #define SRQR_EXACT 1u /* g2 from the exact row norms of Rhat^-1 instead of d Gaussian probes */
@@ -134,6 +148,7 @@ int srqr_workspace_size(int m, int n, int l, const rqrcp_params *prm, int d, uns
                         size_t *bytes);
 
 /* Alg. 3 after an l-step rqrcp_factor (k = l) with the same prm, 1 <= l < min(m, n).
+ * FP64 only (prm->a_type = RQRCP_F64; the swap tests are FP64 in every form).
  *  g          tolerance g > 1 of the g2 test (Section IV-C: g2 = |alpha| ||Rhat^-T||_{1,2}).
  *  d          probe count of the g2 estimate g2 ~ |alpha| ||Omega Rhat^-T||_{1,2} / sqrt(d),
  *             Omega (d x (l+1)) from Philox(prm->seed, stream 2^32 + j) at estimate j

@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(HERE, "librqrcp.so")
 
 F64 = 0
 F32 = 1
+BF16 = 2
+F8E4M3 = 3
+SKETCH_TYPES = {"f64": F64, "bf16": BF16, "fp8": F8E4M3}
 FROZEN_PIVOTS = 1
 USER_SKETCH = 2
 SRQR_EXACT = 1
@@ -42,7 +45,8 @@ PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other")
 
 class Params(ctypes.Structure):
     _fields_ = [("b", ctypes.c_int), ("p", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("a_type", ctypes.c_int), ("flags", ctypes.c_uint)]
+                ("a_type", ctypes.c_int), ("sketch_type", ctypes.c_int),
+                ("flags", ctypes.c_uint)]
 
 
 _lib = None
@@ -65,9 +69,9 @@ def load_library(path: str = LIB_PATH):
         "rqrcp_workspace_size": (i, [i, i, i, P(Params), P(sz)]),
         "rqrcp_limits": (i, [i, P(i), P(i), P(i)]),
         "rqrcp_gaussian": (i, [vp, i, i, u64, u64, vp, i]),
-        "rqrcp_sketch": (i, [vp, i, i, i, u64, vp, i, vp, i, vp, i, vp, sz]),
+        "rqrcp_sketch": (i, [vp, i, i, i, u64, i, vp, i, i, vp, i, vp, i, vp, sz]),
         "rqrcp_factor": (i, [vp, i, i, i, P(Params), vp, i, vp, vp, vp, i, vp, vp, sz]),
-        "rqrcp_form_q": (i, [vp, i, i, i, vp, i, vp, vp, i, vp, sz]),
+        "rqrcp_form_q": (i, [vp, i, i, i, i, vp, i, vp, vp, i, vp, sz]),
         "rqrcp_check": (i, [vp, vp]),
         "srqr_workspace_size": (i, [i, i, i, P(Params), i, ctypes.c_uint, P(sz)]),
         "srqr_swap": (i, [vp, i, i, i, P(Params), ctypes.c_double, i, i, ctypes.c_uint,
@@ -144,10 +148,28 @@ def _ptr(x):
     return ctypes.c_void_p(x.data_ptr()) if x is not None else ctypes.c_void_p(0)
 
 
-def workspace_bytes(m, n, k, b, p, flags=0):
+def _a_type(dtype):
+    torch = _torch()
+    if dtype == torch.float64:
+        return F64
+    if dtype == torch.float32:
+        return F32
+    raise ValueError(f"unsupported matrix dtype {dtype} (float64 or float32)")
+
+
+def _sketch_type(st):
+    if isinstance(st, int):
+        return st
+    try:
+        return SKETCH_TYPES[st]
+    except KeyError:
+        raise ValueError(f"sketch type {st!r}: one of {sorted(SKETCH_TYPES)}") from None
+
+
+def workspace_bytes(m, n, k, b, p, flags=0, a_type=F64, sketch_type=F64):
     lib = load_library()
     out = ctypes.c_size_t()
-    prm = Params(b, p, 0, F64, flags)
+    prm = Params(b, p, 0, a_type, _sketch_type(sketch_type), flags)
     _check(lib.rqrcp_workspace_size(m, n, k, ctypes.byref(prm), ctypes.byref(out)),
            "rqrcp_workspace_size")
     return out.value
@@ -179,18 +201,22 @@ def gaussian(rows, cols, seed, stream=0, device="cuda"):
     return out
 
 
-def sketch(a, l, seed=0, omega=None, ws=None):
-    """B = Omega A (l x n) for a column-major FP64 A."""
+def sketch(a, l, seed=0, omega=None, ws=None, sketch_type="f64"):
+    """B = Omega A (l x n, FP64) for a column-major FP64 or FP32 A."""
     torch = _torch()
-    a = colmajor(a, torch.float64)
+    if a.dtype not in (torch.float64, torch.float32):
+        a = a.to(torch.float64)
+    a = colmajor(a)
     m, n = a.shape
+    at = _a_type(a.dtype)
+    st = _sketch_type(sketch_type)
     h = handle()
     b = empty_colmajor(l, n, torch.float64, a.device)
     if omega is not None:
         omega = colmajor(omega, torch.float64)
-    nbytes = workspace_bytes(m, n, 1, l, 0)
+    nbytes = workspace_bytes(m, n, 1, l, 0, 0, at, st)
     ws = workspace(nbytes, a.device) if ws is None else ws
-    _check(load_library().rqrcp_sketch(h, m, n, l, seed, _ptr(a), _ld(a), _ptr(omega),
+    _check(load_library().rqrcp_sketch(h, m, n, l, seed, at, _ptr(a), _ld(a), st, _ptr(omega),
                                         _ld(omega) if omega is not None else 0, _ptr(b), l,
                                         _ptr(ws), ws.numel()), "rqrcp_sketch")
     return b
@@ -208,20 +234,25 @@ class Factorization:
 
 
 def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=False,
-           check=True):
-    """Truncated RQRCP (Alg. 2) of the FP64 matrix ``a`` to rank ``k``.
+           check=True, sketch_type="f64"):
+    """Truncated RQRCP (Alg. 2) of the FP64 or FP32 matrix ``a`` to rank ``k``.
 
     jpvt: frozen pivots (the columns A(:, jpvt) are factored without pivoting).
     sketch_b: a precomputed sketch Omega A ((b+p) x n), e.g. with a custom Omega.
+    sketch_type: "f64", "bf16" or "fp8" (the arithmetic of B = Omega A).
+    An FP32 ``a`` is the mixed-precision form (FP32 trailing update and storage,
+    FP64 reflectors, sketch and sample update).
     Returns a Factorization with device tensors.
     """
     torch = _torch()
+    if a.dtype not in (torch.float64, torch.float32):
+        a = a.to(torch.float64)
     if inplace:
-        if a.dtype != torch.float64 or a.stride(0) != 1:
-            raise ValueError("inplace needs a column-major float64 tensor")
+        if a.stride(0) != 1:
+            raise ValueError("inplace needs a column-major tensor")
         af = a
     else:
-        af = colmajor(a, torch.float64).clone(memory_format=torch.preserve_format)
+        af = colmajor(a).clone(memory_format=torch.preserve_format)
         if af.stride(0) != 1:
             af = colmajor(af)
     m, n = af.shape
@@ -241,10 +272,11 @@ def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=Fal
         bs = empty_colmajor(b + p, n, torch.float64, dev)
     tau = torch.empty(k, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
-    nbytes = workspace_bytes(m, n, k, b, p, flags)
+    at, st = _a_type(af.dtype), _sketch_type(sketch_type)
+    nbytes = workspace_bytes(m, n, k, b, p, flags, at, st)
     if ws is None or ws.numel() < nbytes:
         ws = workspace(nbytes, dev)
-    prm = Params(b, p, seed, F64, flags)
+    prm = Params(b, p, seed, at, st, flags)
     lib = load_library()
     h = handle()
     _check(lib.rqrcp_factor(h, m, n, k, ctypes.byref(prm), _ptr(af), _ld(af), _ptr(jp),
@@ -255,15 +287,16 @@ def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=Fal
     return Factorization(af, jp, tau, bs, info, k, b)
 
 
-def factor_into(a, k, b, p, seed, jpvt, tau, bsk, info, ws, flags=0):
+def factor_into(a, k, b, p, seed, jpvt, tau, bsk, info, ws, flags=0, sketch_type="f64"):
     """rqrcp_factor on caller-owned device buffers (no allocation, no sync).
 
-    a: column-major float64 (m x n), overwritten; jpvt int32 (n); tau float64 (k);
-    bsk column-major float64 ((b+p) x n) or None with FROZEN_PIVOTS; info int32 (1);
-    ws uint8 workspace of at least workspace_bytes(m, n, k, b, p, flags).
+    a: column-major float64 or float32 (m x n), overwritten; jpvt int32 (n);
+    tau float64 (k); bsk column-major float64 ((b+p) x n) or None with
+    FROZEN_PIVOTS; info int32 (1); ws uint8 workspace of at least
+    workspace_bytes(m, n, k, b, p, flags, a_type, sketch_type).
     """
     m, n = a.shape
-    prm = Params(b, p, seed, F64, flags)
+    prm = Params(b, p, seed, _a_type(a.dtype), _sketch_type(sketch_type), flags)
     _check(load_library().rqrcp_factor(handle(), m, n, k, ctypes.byref(prm), _ptr(a), _ld(a),
                                         _ptr(jpvt), _ptr(tau), _ptr(bsk),
                                         (_ld(bsk) if bsk is not None else b + p), _ptr(info),
@@ -271,15 +304,16 @@ def factor_into(a, k, b, p, seed, jpvt, tau, bsk, info, ws, flags=0):
 
 
 def form_q(fact_a, tau, k=None, b=64, ws=None):
-    """Explicit Q1 (m x k) of a factorization in LAPACK storage."""
+    """Explicit Q1 (m x k) of a factorization in LAPACK storage (FP64 or FP32)."""
     torch = _torch()
     k = tau.numel() if k is None else k
     m = fact_a.shape[0]
-    q = empty_colmajor(m, k, torch.float64, fact_a.device)
-    nbytes = workspace_bytes(m, k, k, b, 0)
+    at = _a_type(fact_a.dtype)
+    q = empty_colmajor(m, k, fact_a.dtype, fact_a.device)
+    nbytes = workspace_bytes(m, k, k, b, 0, 0, at)
     ws = workspace(nbytes, fact_a.device) if ws is None or ws.numel() < nbytes else ws
-    _check(load_library().rqrcp_form_q(handle(), m, k, b, _ptr(fact_a), _ld(fact_a), _ptr(tau),
-                                        _ptr(q), max(1, m), _ptr(ws), ws.numel()),
+    _check(load_library().rqrcp_form_q(handle(), m, k, b, at, _ptr(fact_a), _ld(fact_a),
+                                        _ptr(tau), _ptr(q), max(1, m), _ptr(ws), ws.numel()),
            "rqrcp_form_q")
     return q
 
@@ -311,7 +345,7 @@ def srqr(a0, l, b, p, g, seed=0, *, d=16, exact=False, max_swaps=-1, sketch_b=No
     ns = torch.zeros(1, dtype=torch.int32, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     flags = SRQR_EXACT if exact else 0
-    prm = Params(b, p, seed, F64, 0)
+    prm = Params(b, p, seed, F64, F64, 0)
     lib = load_library()
     nb = ctypes.c_size_t()
     _check(lib.srqr_workspace_size(m, n, l, ctypes.byref(prm), d, flags, ctypes.byref(nb)),

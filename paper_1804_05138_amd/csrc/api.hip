@@ -91,8 +91,11 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t omega, sketch_part, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy, formq, total;
+  size_t omega, sketch_part, sketch_lp, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy,
+      formq, total;
 };
+
+size_t elem_size(int t) { return t == RQRCP_F32 ? sizeof(float) : sizeof(double); }
 
 // Every workspace starts with the scratch words of the persistent kernels, so
 // that rqrcp_check can find their error flags without the call's sizes.
@@ -125,9 +128,11 @@ size_t wpart_doubles(int m, int n, int k, int b) {
   return best;
 }
 
-Layout layout(int m, int n, int k, int b, int p, unsigned flags) {
+Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   Layout L;
-  const int l = b + p;
+  const int b = prm.b, p = prm.p, l = b + p;
+  const unsigned flags = prm.flags;
+  const size_t es = elem_size(prm.a_type);
   size_t off = HEADER;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -136,16 +141,17 @@ Layout layout(int m, int n, int k, int b, int p, unsigned flags) {
   };
   L.omega = take((size_t)l * m * sizeof(double));
   L.sketch_part = take(sketch_partial_doubles(m, n, l) * sizeof(double));
+  L.sketch_lp = take(sketch_lp_bytes(m, n, l, prm.sketch_type));
   L.qscr = QSCR_OFF;
   L.cand = take(qrcp_cand_doubles(l, n) * sizeof(double));
   L.pairs = take(4 * MAX_B * sizeof(int));
   L.pscr = PSCR_OFF;
   L.ppart = take(panel_partial_doubles(m, std::min(b, k)) * sizeof(double));
   L.tmat = take((size_t)MAX_B * MAX_B * sizeof(double));
-  L.wpart = take(wpart_doubles(m, n, k, b) * sizeof(double));
+  L.wpart = take(wpart_doubles(m, n, k, b) * es);
   L.wp = take((size_t)b * n * sizeof(double));
-  L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * sizeof(double) : 0);
-  L.formq = take(form_q_work_elems(m, k, b) * sizeof(double));
+  L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * es : 0);
+  L.formq = take(form_q_work_elems(m, k, b) * es);
   L.total = off;
   return L;
 }
@@ -170,8 +176,9 @@ __global__ void k_init(QrcpScratch* q, PanelScratch* p, int* info, int* jpvt, in
     for (int j = t; j < n; j += gridDim.x * blockDim.x) jpvt[j] = j;
 }
 
-__global__ void k_copy_cols(int m, int n, const double* __restrict__ src, long long lds,
-                            double* __restrict__ dst, long long ldd, const int* __restrict__ perm) {
+template <typename T>
+__global__ void k_copy_cols(int m, int n, const T* __restrict__ src, long long lds,
+                            T* __restrict__ dst, long long ldd, const int* __restrict__ perm) {
   const long long total = (long long)m * n;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
@@ -189,7 +196,153 @@ unsigned grid_for(long long total) {
 }
 
 bool valid_params(const rqrcp_params* prm) {
-  return prm && prm->b >= 1 && prm->p >= 0;
+  return prm && prm->b >= 1 && prm->p >= 0 &&
+         (prm->a_type == RQRCP_F64 || prm->a_type == RQRCP_F32) &&
+         (prm->sketch_type == RQRCP_F64 || prm->sketch_type == RQRCP_BF16 ||
+          prm->sketch_type == RQRCP_F8E4M3);
+}
+
+}  // namespace
+
+namespace {
+
+// The block loop of Alg. 2 for storage type T of A (see the top of the file).
+template <typename T>
+int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, const Layout& L,
+                T* A, int lda, int32_t* jpvt, double* tau, double* B, int ldb, int32_t* info,
+                void* ws) {
+  const int b = prm->b, p = prm->p, l = b + p;
+  (void)p;
+  const bool frozen = (prm->flags & RQRCP_FROZEN_PIVOTS) != 0;
+  hipStream_t s = h->stream;
+  char* w = (char*)ws;
+  double* om = (double*)(w + L.omega);
+  void* sklp = w + L.sketch_lp;
+  double* spart = (double*)(w + L.sketch_part);
+  QrcpScratch* qscr = (QrcpScratch*)(w + L.qscr);
+  double* cand = (double*)(w + L.cand);
+  int* pairs = (int*)(w + L.pairs);
+  PanelScratch* pscr = (PanelScratch*)(w + L.pscr);
+  double* ppart = (double*)(w + L.ppart);
+  double* tmat = (double*)(w + L.tmat);
+  T* wpart = (T*)(w + L.wpart);
+  double* wp = (double*)(w + L.wp);
+  const long long ldw = b;
+  int rc;
+
+  hipLaunchKernelGGL(k_init, dim3(grid_for(n)), dim3(256), 0, s, qscr, pscr, info, jpvt, n,
+                     frozen ? 0 : 1, cand, frozen ? 0LL : (long long)qrcp_cand_doubles(l, n));
+  RQ_HIP_CHECK(hipGetLastError());
+
+  if (frozen) {
+    T* cp = (T*)(w + L.copy);
+    hipLaunchKernelGGL(k_copy_cols<T>, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n,
+                       (const T*)A, (long long)lda, cp, (long long)m, (const int*)nullptr);
+    hipLaunchKernelGGL(k_copy_cols<T>, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n,
+                       (const T*)cp, (long long)m, A, (long long)lda, (const int*)jpvt);
+    RQ_HIP_CHECK(hipGetLastError());
+  } else if (!(prm->flags & RQRCP_USER_SKETCH)) {
+    PhaseTimer pt(h, RQRCP_PHASE_SKETCH, 2.0 * l * (double)m * n,
+                  8.0 * ((double)m * n + (double)l * n));
+    rc = launch_gaussian(s, l, m, prm->seed, 0, om, l);
+    if (rc) return rc;
+    rc = launch_sketch<T>(s, m, n, l, prm->sketch_type, om, l, A, lda, B, ldb, spart, sklp);
+    if (rc) return rc;
+  }
+
+  // algorithmic work of one launch of each phase
+  auto qrcp_flops = [&](int nc, int steps) {
+    double f = 0.0;
+    for (int t = 0; t < steps; ++t) f += 4.0 * (l - t) * (double)(nc - t);
+    return f;
+  };
+  auto panel_flops = [&](int rows, int w, int wprev) {
+    return 3.0 * rows * (double)w * w + 2.0 * (rows + wprev) * (double)wprev * w;
+  };
+  auto trail_flops = [&](int ii, int bbu, int bbn, int ncols) {
+    return 2.0 * (m - ii) * (double)bbu * ncols + 2.0 * (m - ii - bbu) * (double)bbn * ncols;
+  };
+
+  int i = 0;
+  int bb = std::min(b, k);
+  int nsp = 0;
+  if (!frozen) {
+    {
+      PhaseTimer pt(h, RQRCP_PHASE_QRCP, qrcp_flops(n, bb), 16.0 * l * (double)n);
+      rc = launch_qrcp_sketch(s, B, ldb, l, 0, n, bb, 0, qscr, cand, pairs, info);
+      if (rc) return rc;
+    }
+    PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
+    rc = launch_apply_pairs<T>(s, m, A, lda, 0, jpvt, nullptr, 0, 0, 0, pairs, &qscr->npairs,
+                               2 * bb);
+    if (rc) return rc;
+  }
+  {
+    PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m, bb, 0), 16.0 * m * (double)bb);
+    rc = launch_panel<T>(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart);
+    if (rc) return rc;
+  }
+  if (n - bb > 0) {
+    PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(0, 0, bb, n - bb), 8.0 * m * (double)(n - bb));
+    TrailPlan pl = trail_plan(m, n - bb);
+    rc = launch_trail<T>(s, m, A, lda, 0, 0, bb, (const double*)nullptr, 0, 0, bb, n, wpart,
+                         pl.nsplit, &nsp);
+    if (rc) return rc;
+  }
+  for (;;) {
+    const int c0 = i + bb;
+    const int ncols = n - c0;
+    if (ncols > 0) {
+      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * bb * (double)bb * ncols,
+                    8.0 * ncols * (double)bb * (nsp + 4));
+      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, wpart, nsp, wp, ldw, frozen ? nullptr : B,
+                          ldb, c0, ncols, info);
+      if (rc) return rc;
+    }
+    if (c0 < k) {
+      const int bbn = std::min(b, k - c0);
+      if (!frozen) {
+        {
+          PhaseTimer pt(h, RQRCP_PHASE_QRCP, qrcp_flops(ncols, bbn), 16.0 * l * (double)ncols);
+          rc = launch_qrcp_sketch(s, B, ldb, l, c0, ncols, bbn, c0, qscr, cand, pairs, info);
+          if (rc) return rc;
+        }
+        PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
+        rc = launch_apply_pairs<T>(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs,
+                                   &qscr->npairs, 2 * bbn);
+        if (rc) return rc;
+      }
+      {
+        PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m - c0, bbn, bb),
+                      16.0 * (m - i) * (double)bbn);
+        rc = launch_panel<T>(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart);
+        if (rc) return rc;
+      }
+      const int nrest = n - (c0 + bbn);
+      if (nrest > 0) {
+        PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, bbn, nrest),
+                      16.0 * (m - i) * (double)nrest);
+        TrailPlan pl = trail_plan(m - i, nrest);
+        rc = launch_trail<T>(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw, c0 + bbn,
+                              c0 + bbn, n, wpart, pl.nsplit, &nsp);
+        if (rc) return rc;
+      } else {
+        nsp = 0;
+      }
+      i = c0;
+      bb = bbn;
+    } else {
+      if (ncols > 0) {
+        PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, 0, ncols),
+                      16.0 * (m - i) * (double)ncols);
+        int dummy = 0;
+        rc = launch_trail<T>(s, m, A, lda, i, bb, 0, wp, ldw, c0, c0, n, (T*)nullptr, 1, &dummy);
+        if (rc) return rc;
+      }
+      break;
+    }
+  }
+  return 0;
 }
 
 }  // namespace
@@ -246,7 +399,7 @@ int rqrcp_workspace_size(int m, int n, int k, const rqrcp_params* prm, size_t* b
   if (k < 1 || k > std::min(m, n)) return -3;
   if (!valid_params(prm)) return -4;
   if (!bytes) return -5;
-  *bytes = layout(m, n, k, prm->b, prm->p, prm->flags).total;
+  *bytes = layout(m, n, k, *prm).total;
   return 0;
 }
 
@@ -260,23 +413,29 @@ int rqrcp_gaussian(rqrcp_handle h, int rows, int cols, uint64_t seed, uint64_t s
   return launch_gaussian(h->stream, rows, cols, seed, stream, out, ld);
 }
 
-int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, const double* A, int lda,
-                 const double* Omega, int ldo, double* B, int ldb, void* ws, size_t ws_bytes) {
+int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, int a_type, const void* A,
+                 int lda, int sketch_type, const double* Omega, int ldo, double* B, int ldb,
+                 void* ws, size_t ws_bytes) {
   if (!h) return -1;
   if (m < 1) return -2;
   if (n < 1) return -3;
   if (l < 1 || l > MAX_L) return -4;
-  if (!A) return -6;
-  if (lda < m) return -7;
-  if (Omega && ldo < l) return -9;
-  if (!B) return -10;
-  if (ldb < l) return -11;
-  const size_t need = HEADER + align_up((size_t)l * m * sizeof(double)) +
-                      align_up(sketch_partial_doubles(m, n, l) * sizeof(double));
+  if (a_type != RQRCP_F64 && a_type != RQRCP_F32) return -6;
+  if (!A) return -7;
+  if (lda < m) return -8;
+  if (sketch_type != RQRCP_F64 && sketch_type != RQRCP_BF16 && sketch_type != RQRCP_F8E4M3)
+    return -9;
+  if (Omega && ldo < l) return -11;
+  if (!B) return -12;
+  if (ldb < l) return -13;
+  const size_t om_b = align_up((size_t)l * m * sizeof(double));
+  const size_t part_b = align_up(sketch_partial_doubles(m, n, l) * sizeof(double));
+  const size_t need = HEADER + om_b + part_b + sketch_lp_bytes(m, n, l, sketch_type);
   if (!ws || ws_bytes < need) return RQRCP_ERR_WORKSPACE;
   char* w = (char*)ws + HEADER;
   double* om = (double*)w;
-  double* part = (double*)(w + align_up((size_t)l * m * sizeof(double)));
+  double* part = (double*)(w + om_b);
+  void* lp = w + om_b + part_b;
   long long ldo_eff = ldo;
   if (!Omega) {
     int rc = launch_gaussian(h->stream, l, m, seed, 0, om, l);
@@ -284,10 +443,14 @@ int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, const doubl
     Omega = om;
     ldo_eff = l;
   }
-  return launch_sketch_f64(h->stream, m, n, l, Omega, ldo_eff, A, lda, B, ldb, part);
+  if (a_type == RQRCP_F64)
+    return launch_sketch<double>(h->stream, m, n, l, sketch_type, Omega, ldo_eff,
+                                 (const double*)A, lda, B, ldb, part, lp);
+  return launch_sketch<float>(h->stream, m, n, l, sketch_type, Omega, ldo_eff, (const float*)A,
+                              lda, B, ldb, part, lp);
 }
 
-int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, double* A, int lda,
+int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, void* A, int lda,
                  int32_t* jpvt, double* tau, double* B, int ldb, int32_t* info, void* ws,
                  size_t ws_bytes) {
   if (!h) return -1;
@@ -298,7 +461,6 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, d
   const int b = prm->b, p = prm->p, l = b + p;
   const bool frozen = (prm->flags & RQRCP_FROZEN_PIVOTS) != 0;
   if (b > MAX_B || l > MAX_L) return RQRCP_ERR_LIMIT;
-  if (prm->a_type != RQRCP_F64) return RQRCP_ERR_UNSUPPORTED;
   if (!A) return -6;
   if (lda < m) return -7;
   if (!jpvt) return -8;
@@ -306,7 +468,7 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, d
   if (!frozen && !B) return -10;
   if (!frozen && ldb < l) return -11;
   if (!info) return -12;
-  const Layout L = layout(m, n, k, b, p, prm->flags);
+  const Layout L = layout(m, n, k, *prm);
   if (!ws || ws_bytes < L.total) return RQRCP_ERR_WORKSPACE;
   if (!frozen) {
     int maxn = 0;
@@ -314,133 +476,9 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, d
     if (n > maxn) return RQRCP_ERR_LIMIT;
   }
 
-  hipStream_t s = h->stream;
-  char* w = (char*)ws;
-  double* om = (double*)(w + L.omega);
-  double* spart = (double*)(w + L.sketch_part);
-  QrcpScratch* qscr = (QrcpScratch*)(w + L.qscr);
-  double* cand = (double*)(w + L.cand);
-  int* pairs = (int*)(w + L.pairs);
-  PanelScratch* pscr = (PanelScratch*)(w + L.pscr);
-  double* ppart = (double*)(w + L.ppart);
-  double* tmat = (double*)(w + L.tmat);
-  double* wpart = (double*)(w + L.wpart);
-  double* wp = (double*)(w + L.wp);
-  const long long ldw = b;
-  int rc;
-
-  hipLaunchKernelGGL(k_init, dim3(grid_for(n)), dim3(256), 0, s, qscr, pscr, info, jpvt, n,
-                     frozen ? 0 : 1, cand, frozen ? 0LL : (long long)qrcp_cand_doubles(l, n));
-  RQ_HIP_CHECK(hipGetLastError());
-
-  if (frozen) {
-    double* cp = (double*)(w + L.copy);
-    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n,
-                       (const double*)A, (long long)lda, cp, (long long)m, (const int*)nullptr);
-    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n,
-                       (const double*)cp, (long long)m, A, (long long)lda, (const int*)jpvt);
-    RQ_HIP_CHECK(hipGetLastError());
-  } else if (!(prm->flags & RQRCP_USER_SKETCH)) {
-    PhaseTimer pt(h, RQRCP_PHASE_SKETCH, 2.0 * l * (double)m * n,
-                  8.0 * ((double)m * n + (double)l * n));
-    rc = launch_gaussian(s, l, m, prm->seed, 0, om, l);
-    if (rc) return rc;
-    rc = launch_sketch_f64(s, m, n, l, om, l, A, lda, B, ldb, spart);
-    if (rc) return rc;
-  }
-
-  // algorithmic work of one launch of each phase
-  auto qrcp_flops = [&](int nc, int steps) {
-    double f = 0.0;
-    for (int t = 0; t < steps; ++t) f += 4.0 * (l - t) * (double)(nc - t);
-    return f;
-  };
-  auto panel_flops = [&](int rows, int w, int wprev) {
-    return 3.0 * rows * (double)w * w + 2.0 * (rows + wprev) * (double)wprev * w;
-  };
-  auto trail_flops = [&](int ii, int bbu, int bbn, int ncols) {
-    return 2.0 * (m - ii) * (double)bbu * ncols + 2.0 * (m - ii - bbu) * (double)bbn * ncols;
-  };
-
-  int i = 0;
-  int bb = std::min(b, k);
-  int nsp = 0;
-  if (!frozen) {
-    {
-      PhaseTimer pt(h, RQRCP_PHASE_QRCP, qrcp_flops(n, bb), 16.0 * l * (double)n);
-      rc = launch_qrcp_sketch(s, B, ldb, l, 0, n, bb, 0, qscr, cand, pairs, info);
-      if (rc) return rc;
-    }
-    PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
-    rc = launch_apply_pairs(s, m, A, lda, 0, jpvt, nullptr, 0, 0, 0, pairs, &qscr->npairs,
-                            2 * bb, nullptr);
-    if (rc) return rc;
-  }
-  {
-    PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m, bb, 0), 16.0 * m * (double)bb);
-    rc = launch_panel(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart);
-    if (rc) return rc;
-  }
-  if (n - bb > 0) {
-    PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(0, 0, bb, n - bb), 8.0 * m * (double)(n - bb));
-    TrailPlan pl = trail_plan(m, n - bb);
-    rc = launch_trail_f64(s, m, A, lda, 0, 0, bb, nullptr, 0, 0, bb, n, wpart, pl.nsplit, &nsp);
-    if (rc) return rc;
-  }
-  for (;;) {
-    const int c0 = i + bb;
-    const int ncols = n - c0;
-    if (ncols > 0) {
-      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * bb * (double)bb * ncols,
-                    8.0 * ncols * (double)bb * (nsp + 4));
-      rc = launch_bupdate(s, m, A, lda, i, bb, tmat, wpart, nsp, wp, ldw, frozen ? nullptr : B,
-                          ldb, c0, ncols, info);
-      if (rc) return rc;
-    }
-    if (c0 < k) {
-      const int bbn = std::min(b, k - c0);
-      if (!frozen) {
-        {
-          PhaseTimer pt(h, RQRCP_PHASE_QRCP, qrcp_flops(ncols, bbn), 16.0 * l * (double)ncols);
-          rc = launch_qrcp_sketch(s, B, ldb, l, c0, ncols, bbn, c0, qscr, cand, pairs, info);
-          if (rc) return rc;
-        }
-        PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
-        rc = launch_apply_pairs(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs, &qscr->npairs,
-                                2 * bbn, nullptr);
-        if (rc) return rc;
-      }
-      {
-        PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m - c0, bbn, bb),
-                      16.0 * (m - i) * (double)bbn);
-        rc = launch_panel(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart);
-        if (rc) return rc;
-      }
-      const int nrest = n - (c0 + bbn);
-      if (nrest > 0) {
-        PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, bbn, nrest),
-                      16.0 * (m - i) * (double)nrest);
-        TrailPlan pl = trail_plan(m - i, nrest);
-        rc = launch_trail_f64(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw, c0 + bbn,
-                              c0 + bbn, n, wpart, pl.nsplit, &nsp);
-        if (rc) return rc;
-      } else {
-        nsp = 0;
-      }
-      i = c0;
-      bb = bbn;
-    } else {
-      if (ncols > 0) {
-        PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, 0, ncols),
-                      16.0 * (m - i) * (double)ncols);
-        int dummy = 0;
-        rc = launch_trail_f64(s, m, A, lda, i, bb, 0, wp, ldw, c0, c0, n, nullptr, 1, &dummy);
-        if (rc) return rc;
-      }
-      break;
-    }
-  }
-  return 0;
+  if (prm->a_type == RQRCP_F32)
+    return factor_impl<float>(h, m, n, k, prm, L, (float*)A, lda, jpvt, tau, B, ldb, info, ws);
+  return factor_impl<double>(h, m, n, k, prm, L, (double*)A, lda, jpvt, tau, B, ldb, info, ws);
 }
 
 int srqr_workspace_size(int m, int n, int l, const rqrcp_params* prm, int d, unsigned sflags,
@@ -451,7 +489,9 @@ int srqr_workspace_size(int m, int n, int l, const rqrcp_params* prm, int d, uns
   if (!valid_params(prm)) return -4;
   if (d < 1 && !(sflags & SRQR_EXACT)) return -5;
   if (!bytes) return -7;
-  const size_t fac = align_up(layout(m, n, l + 1, prm->b, prm->p, RQRCP_FROZEN_PIVOTS).total);
+  rqrcp_params fprm = *prm;
+  fprm.flags = RQRCP_FROZEN_PIVOTS;
+  const size_t fac = align_up(layout(m, n, l + 1, fprm).total);
   *bytes = fac + srqr_layout(m, n, l, d, (sflags & SRQR_EXACT) ? 1 : 0).total;
   return 0;
 }
@@ -465,6 +505,7 @@ int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params* prm, doub
   if (n < 1) return -3;
   if (l < 1 || l >= std::min(m, n)) return -4;
   if (!valid_params(prm) || prm->b > MAX_B) return -5;
+  if (prm->a_type != RQRCP_F64) return RQRCP_ERR_UNSUPPORTED;
   if (!(g > 1.0)) return -6;
   const int exact = (sflags & SRQR_EXACT) ? 1 : 0;
   if (!exact && d < 1) return -7;
@@ -484,7 +525,9 @@ int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params* prm, doub
   if (!ws || ws_bytes < need) return RQRCP_ERR_WORKSPACE;
   if (max_swaps < 0) max_swaps = 2 * n;
   hipStream_t s = h->stream;
-  const size_t fac = align_up(layout(m, n, l + 1, prm->b, prm->p, RQRCP_FROZEN_PIVOTS).total);
+  rqrcp_params fprm = *prm;
+  fprm.flags = RQRCP_FROZEN_PIVOTS;
+  const size_t fac = align_up(layout(m, n, l + 1, fprm).total);
   char* sw = (char*)ws + fac;
   const SrqrLayout L = srqr_layout(m, n, l, d, exact);
   double* est = (double*)(sw + L.est);
@@ -535,12 +578,10 @@ int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params* prm, doub
   }
   if (nswaps > 0) {
     // Givens rotations are not representable by (V, tau): refactor A0(:, jpvt)
-    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n, A0,
+    hipLaunchKernelGGL(k_copy_cols<double>, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n, A0,
                        (long long)lda0, A, (long long)lda, (const int*)nullptr);
     RQ_HIP_CHECK(hipGetLastError());
-    rqrcp_params fp = *prm;
-    fp.flags = RQRCP_FROZEN_PIVOTS;
-    rc = rqrcp_factor(h, m, n, l + 1, &fp, A, lda, jpvt, tau, nullptr, 0, info, ws, fac);
+    rc = rqrcp_factor(h, m, n, l + 1, &fprm, A, lda, jpvt, tau, nullptr, 0, info, ws, fac);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, info, (g2 > g) ? -max_swaps : 0);
@@ -549,20 +590,26 @@ int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params* prm, doub
   return 0;
 }
 
-int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, const double* A, int lda, const double* tau,
-                 double* Q, int ldq, void* ws, size_t ws_bytes) {
+int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, int a_type, const void* A, int lda,
+                 const double* tau, void* Q, int ldq, void* ws, size_t ws_bytes) {
   if (!h) return -1;
   if (m < 1) return -2;
   if (k < 1 || k > m) return -3;
   if (b < 1 || b > MAX_B) return -4;
-  if (!A) return -5;
-  if (lda < m) return -6;
-  if (!tau) return -7;
-  if (!Q) return -8;
-  if (ldq < m) return -9;
-  if (!ws || ws_bytes < HEADER + form_q_work_elems(m, k, b) * sizeof(double))
+  if (a_type != RQRCP_F64 && a_type != RQRCP_F32) return -5;
+  if (!A) return -6;
+  if (lda < m) return -7;
+  if (!tau) return -8;
+  if (!Q) return -9;
+  if (ldq < m) return -10;
+  if (!ws || ws_bytes < HEADER + form_q_work_elems(m, k, b) * elem_size(a_type))
     return RQRCP_ERR_WORKSPACE;
-  return launch_form_q(h->stream, m, k, b, A, lda, tau, Q, ldq, (double*)((char*)ws + HEADER));
+  void* work = (char*)ws + HEADER;
+  if (a_type == RQRCP_F32)
+    return form_q<float>(h->stream, m, k, b, (const float*)A, lda, tau, (float*)Q, ldq,
+                         (float*)work);
+  return form_q<double>(h->stream, m, k, b, (const double*)A, lda, tau, (double*)Q, ldq,
+                        (double*)work);
 }
 
 int rqrcp_check(rqrcp_handle h, void* ws) {

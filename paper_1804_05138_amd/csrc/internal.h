@@ -28,11 +28,18 @@ constexpr int MAX_L = 160;      // largest b + p the kernels accept
 int launch_gaussian(hipStream_t s, int rows, int cols, uint64_t seed, uint64_t stream,
                     double* out, long long ld);
 
-// B(0:l, 0:n) = Omega(0:l, 0:m) * A(0:m, 0:n), all FP64 column-major.
-// `partial` holds split-K partial products (size partial_size_f64(...) doubles).
+// B(0:l, 0:n) = Omega(0:l, 0:m) * A(0:m, 0:n), column-major; A in FP64 or
+// FP32, Omega and B in FP64.  stype: SK_F64 (FP64 MFMA), SK_BF16 or SK_FP8
+// (low-precision MFMA, FP32 accumulation).  `partial` holds split-K partial
+// products (sketch_partial_doubles), `lpbuf` the rounded Omega and the FP8
+// column scales (sketch_lp_bytes).
+enum { SK_F64 = 0, SK_BF16 = 2, SK_FP8 = 3 };
 size_t sketch_partial_doubles(int m, int n, int l);
-int launch_sketch_f64(hipStream_t s, int m, int n, int l, const double* om, long long ldo,
-                      const double* a, long long lda, double* b, long long ldb, double* partial);
+size_t sketch_lp_bytes(int m, int n, int l, int stype);
+template <typename TA>
+int launch_sketch(hipStream_t s, int m, int n, int l, int stype, const double* om, long long ldo,
+                  const TA* a, long long lda, double* b, long long ldb, double* partial,
+                  void* lpbuf);
 
 // Partial QRCP (Alg. 1) on the l x nc block of B starting at column c0.
 // On exit B holds the transformed block with its columns in pivot order;
@@ -46,15 +53,18 @@ size_t qrcp_cand_doubles(int l, int nc);
 
 // Column moves from `pairs` (count at *npairs) applied to A(0:m, c0 + .),
 // jpvt(c0 + .) and W'(0:wrows, w0 + .) (W' may be null).
-int launch_apply_pairs(hipStream_t s, int m, double* a, long long lda, int c0, int* jpvt,
-                       double* wp, int wrows, long long ldw, int w0, const int* pairs,
-                       const int* npairs, int max_pairs, double* tmp);
+template <typename T>
+int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* jpvt, double* wp,
+                       int wrows, long long ldw, int w0, const int* pairs, const int* npairs,
+                       int max_pairs);
 
 // Panel QR of A(i:m, i:i+bb) with the previous block's pending update
 // A(ip:m, i:i+bb) -= Vprev * Wp(:, 0:bb) applied first (if bbp > 0, ip = i - bbp).
 // Writes V/R in place, tau(i:i+bb) and T (bb x bb, column-major, ld bb).
+// T is the storage type of A (double or float); the arithmetic is FP64.
 int panel_grid(int rows, int bb);
-int launch_panel(hipStream_t s, int m, double* a, long long lda, int i, int bb, int bbp,
+template <typename T>
+int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
                  const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
                  double* partial);
 size_t panel_partial_doubles(int rows, int bb);
@@ -68,16 +78,19 @@ struct TrailPlan {
   int ntiles;
 };
 TrailPlan trail_plan(int m_rows, int ncols);
-int launch_trail_f64(hipStream_t s, int m, double* a, long long lda, int i, int bbu, int bbn,
-                     const double* wp, long long ldw, int w0, int c_begin, int c_end,
-                     double* wpart, int nsplit, int* nsp_out);
+// T = double: FP64 MFMA; T = float: FP32 MFMA (W' is rounded to FP32).
+template <typename T>
+int launch_trail(hipStream_t s, int m, T* a, long long lda, int i, int bbu, int bbn,
+                 const double* wp, long long ldw, int w0, int c_begin, int c_end, T* wpart,
+                 int nsplit, int* nsp_out);
 
 // From the split partials of W = V^T A2 (bb x ncols): W' = T^T W (stored at wp),
 // then R12 = A(i:i+bb, c) - V11 W'(:, c), X = R11^-1 R12 and
 // B(0:bb, c) -= Rhat11 X for the columns c = c0 .. c0 + ncols - 1 (skipped when
 // *info != 0).  Rhat11 = triu(B(0:bb, i:i+bb)).
-int launch_bupdate(hipStream_t s, int m, const double* a, long long lda, int i, int bb,
-                   const double* t, const double* wpart, int nsplit, double* wp, long long ldw,
+template <typename T>
+int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int bb,
+                   const double* t, const T* wpart, int nsplit, double* wp, long long ldw,
                    double* bsk, long long ldb, int c0, int ncols, const int* info);
 
 // Explicit Q1 = H_0 ... H_{k-1} [I; 0] (m x k) from LAPACK storage.

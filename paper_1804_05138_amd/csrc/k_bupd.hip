@@ -18,9 +18,10 @@ namespace {
 
 constexpr int BT = 256;
 
-__global__ __launch_bounds__(BT) void k_bupdate(int m, const double* __restrict__ a, long long lda,
+template <typename T>
+__global__ __launch_bounds__(BT) void k_bupdate(int m, const T* __restrict__ a, long long lda,
                                                 int i, int bb, const double* __restrict__ tm,
-                                                const double* __restrict__ wpart, int nsplit,
+                                                const T* __restrict__ wpart, int nsplit,
                                                 double* __restrict__ wp, long long ldw,
                                                 double* __restrict__ bsk, long long ldb, int c0,
                                                 int ncols, const int* __restrict__ info) {
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(BT) void k_bupdate(int m, const double* __restrict_
   for (int q = part; q < bb; q += 4) {
     double s = 0.0;
     if (ok)
-      for (int sp = 0; sp < nsplit; ++sp) s += wpart[((long long)sp * ncols + cl) * bb + q];
+      for (int sp = 0; sp < nsplit; ++sp) s += (double)wpart[((long long)sp * ncols + cl) * bb + q];
     v0[q * 64 + lane] = s;
   }
   __syncthreads();
@@ -51,8 +52,8 @@ __global__ __launch_bounds__(BT) void k_bupdate(int m, const double* __restrict_
   if (bsk == nullptr || *info != 0) return;
   // R12 = A(i:i+bb, col) - V11 W'
   for (int r = part; r < bb; r += 4) {
-    double s = ok ? a[(long long)col * lda + i + r] - v1[r * 64 + lane] : 0.0;
-    for (int q = 0; q < r; ++q) s -= a[(long long)(i + q) * lda + i + r] * v1[q * 64 + lane];
+    double s = ok ? (double)a[(long long)col * lda + i + r] - v1[r * 64 + lane] : 0.0;
+    for (int q = 0; q < r; ++q) s -= (double)a[(long long)(i + q) * lda + i + r] * v1[q * 64 + lane];
     v0[r * 64 + lane] = s;
   }
   __syncthreads();
@@ -60,8 +61,9 @@ __global__ __launch_bounds__(BT) void k_bupdate(int m, const double* __restrict_
   if (part == 0) {
     for (int r = bb - 1; r >= 0; --r) {
       double s = v0[r * 64 + lane];
-      for (int q = r + 1; q < bb; ++q) s -= a[(long long)(i + q) * lda + i + r] * v1[q * 64 + lane];
-      v1[r * 64 + lane] = s / a[(long long)(i + r) * lda + i + r];
+      for (int q = r + 1; q < bb; ++q)
+        s -= (double)a[(long long)(i + q) * lda + i + r] * v1[q * 64 + lane];
+      v1[r * 64 + lane] = s / (double)a[(long long)(i + r) * lda + i + r];
     }
   }
   __syncthreads();
@@ -77,15 +79,22 @@ __global__ __launch_bounds__(BT) void k_bupdate(int m, const double* __restrict_
 
 }  // namespace
 
-int launch_bupdate(hipStream_t s, int m, const double* a, long long lda, int i, int bb,
-                   const double* t, const double* wpart, int nsplit, double* wp, long long ldw,
+template <typename T>
+int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int bb,
+                   const double* t, const T* wpart, int nsplit, double* wp, long long ldw,
                    double* bsk, long long ldb, int c0, int ncols, const int* info) {
   if (ncols <= 0) return RQ_OK;
   if (bb > MAX_B) return RQ_ERR_LIMIT;
-  hipLaunchKernelGGL(k_bupdate, dim3((ncols + 63) / 64), dim3(BT), 0, s, m, a, lda, i, bb, t,
+  hipLaunchKernelGGL(k_bupdate<T>, dim3((ncols + 63) / 64), dim3(BT), 0, s, m, a, lda, i, bb, t,
                      wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
+template int launch_bupdate<double>(hipStream_t, int, const double*, long long, int, int,
+                                    const double*, const double*, int, double*, long long,
+                                    double*, long long, int, int, const int*);
+template int launch_bupdate<float>(hipStream_t, int, const float*, long long, int, int,
+                                   const double*, const float*, int, double*, long long, double*,
+                                   long long, int, int, const int*);
 
 }  // namespace rq

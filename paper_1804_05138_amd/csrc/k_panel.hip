@@ -1,5 +1,7 @@
 // Householder QR of the pivoted panel (Alg. 2 "unpivoted QR on
 // A(i:m, i:i+b-1)"; PDGEQRF in Alg. 4) and its compact-WY factor T (PDLARFT).
+// The arithmetic is FP64 for both storage types of A: an FP32 panel is
+// widened on load and R, V are rounded to FP32 on the way back.
 //
 // One persistent, co-resident grid; each workgroup keeps a contiguous slab of
 // panel rows in LDS for the whole call.  Reflector t needs one global
@@ -22,7 +24,8 @@ namespace {
 constexpr int PT = 256;
 constexpr int VCH = 16;  // rows per chunk of the pending-update pass
 
-__global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, long long lda,
+template <typename T>
+__global__ __launch_bounds__(PT, 1) void k_panel(int m, T* __restrict__ a, long long lda,
                                                  int i, int bb, int bbp,
                                                  const double* __restrict__ wp, long long ldw,
                                                  double* __restrict__ tau, double* __restrict__ tmat,
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
   // ---- load the slab ----
   for (int e = tid; e < nr * bb; e += PT) {
     const int c = e / nr, r = e % nr;
-    P[r * ldp + c] = a[(long long)(i + c) * lda + rs + r];
+    P[r * ldp + c] = (double)a[(long long)(i + c) * lda + rs + r];
   }
   __syncthreads();
 
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
         double v = 0.0;
         if (ch + rr < nr) {
           const int d = r - rp;
-          v = (d > q) ? a[(long long)(rp + q) * lda + r] : (d == q ? 1.0 : 0.0);
+          v = (d > q) ? (double)a[(long long)(rp + q) * lda + r] : (d == q ? 1.0 : 0.0);
         }
         Vc[rr * bbp + q] = v;
       }
@@ -177,28 +180,27 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, double* __restrict__ a, 
   // ---- write the slab back ----
   for (int e = tid; e < nr * bb; e += PT) {
     const int c = e / nr, r = e % nr;
-    a[(long long)(i + c) * lda + rs + r] = P[r * ldp + c];
+    a[(long long)(i + c) * lda + rs + r] = (T)P[r * ldp + c];
   }
 
   // ---- T from the stored (V^T v_t) columns (forward, columnwise); workgroup 0
   // wrote every tau and gz entry itself ----
   if (g == 0) {
     __syncthreads();
-    double* T = s_red;  // bb <= 128 needs bb*bb doubles: use the panel slab instead
-    T = P;
-    for (int e = tid; e < bb * bb; e += PT) T[e] = 0.0;
+    double* Tm = P;  // bb x bb: the panel slab is free by now
+    for (int e = tid; e < bb * bb; e += PT) Tm[e] = 0.0;
     __syncthreads();
     for (int t = 0; t < bb; ++t) {
       const double tt = tau[i + t];
       if (tid < t) {
         double acc = 0.0;
-        for (int c = tid; c < t; ++c) acc += T[c * bb + tid] * gz[t * bb + c];
-        T[t * bb + tid] = -tt * acc;
+        for (int c = tid; c < t; ++c) acc += Tm[c * bb + tid] * gz[t * bb + c];
+        Tm[t * bb + tid] = -tt * acc;
       }
-      if (tid == t) T[t * bb + t] = tt;
+      if (tid == t) Tm[t * bb + t] = tt;
       __syncthreads();
     }
-    for (int e = tid; e < bb * bb; e += PT) tmat[e] = T[e];
+    for (int e = tid; e < bb * bb; e += PT) tmat[e] = Tm[e];
   }
 }
 
@@ -223,7 +225,8 @@ int panel_grid(int rows, int bb) {
   return (rows + R - 1) / R;
 }
 
-int launch_panel(hipStream_t s, int m, double* a, long long lda, int i, int bb, int bbp,
+template <typename T>
+int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
                  const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
                  double* partial) {
   if (bb < 1 || bb > MAX_B || bbp < 0 || bbp > MAX_B) return RQ_ERR_LIMIT;
@@ -235,16 +238,22 @@ int launch_panel(hipStream_t s, int m, double* a, long long lda, int i, int bb, 
   int dev = 0, ncu = 0, per_cu = 0;
   RQ_HIP_CHECK(hipGetDevice(&dev));
   RQ_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel),
+  RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   RQ_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(&k_panel), PT, shmem));
+      &per_cu, reinterpret_cast<const void*>(&k_panel<T>), PT, shmem));
   // the grid barrier needs every workgroup resident at once
   if (G > ncu * per_cu) return RQ_ERR_LIMIT;
-  hipLaunchKernelGGL(k_panel, dim3(G), dim3(PT), shmem, s, m, a, lda, i, bb, bbp, wp, ldw, tau, t,
+  hipLaunchKernelGGL(k_panel<T>, dim3(G), dim3(PT), shmem, s, m, a, lda, i, bb, bbp, wp, ldw, tau, t,
                      &scr->bar, partial, R);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
+template int launch_panel<double>(hipStream_t, int, double*, long long, int, int, int,
+                                  const double*, long long, double*, double*, PanelScratch*,
+                                  double*);
+template int launch_panel<float>(hipStream_t, int, float*, long long, int, int, int,
+                                 const double*, long long, double*, double*, PanelScratch*,
+                                 double*);
 
 }  // namespace rq

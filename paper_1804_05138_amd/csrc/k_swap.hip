@@ -35,12 +35,13 @@ __global__ __launch_bounds__(ST) void k_apply_pairs(int rows, T* __restrict__ a,
 
 }  // namespace
 
-int launch_apply_pairs(hipStream_t s, int m, double* a, long long lda, int c0, int* jpvt,
-                       double* wp, int wrows, long long ldw, int w0, const int* pairs,
-                       const int* npairs, int max_pairs, double* /*tmp*/) {
+template <typename T>
+int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* jpvt, double* wp,
+                       int wrows, long long ldw, int w0, const int* pairs, const int* npairs,
+                       int max_pairs) {
   if (max_pairs > 2 * MAX_B) return RQ_ERR_LIMIT;
   if (m > 0)
-    hipLaunchKernelGGL(k_apply_pairs<double>, dim3((m + SLAB - 1) / SLAB), dim3(ST), 0, s, m, a,
+    hipLaunchKernelGGL(k_apply_pairs<T>, dim3((m + SLAB - 1) / SLAB), dim3(ST), 0, s, m, a,
                        lda, c0, pairs, npairs);
   if (wp != nullptr && wrows > 0)
     hipLaunchKernelGGL(k_apply_pairs<double>, dim3((wrows + SLAB - 1) / SLAB), dim3(ST), 0, s,
@@ -51,5 +52,9 @@ int launch_apply_pairs(hipStream_t s, int m, double* a, long long lda, int c0, i
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
+template int launch_apply_pairs<double>(hipStream_t, int, double*, long long, int, int*, double*,
+                                        int, long long, int, const int*, const int*, int);
+template int launch_apply_pairs<float>(hipStream_t, int, float*, long long, int, int*, double*,
+                                       int, long long, int, const int*, const int*, int);
 
 }  // namespace rq

@@ -1,6 +1,8 @@
 // Trailing-matrix update of Alg. 2 ("A(i:m, i+b:n) <- Q~^T A(i:m, i+b:n)",
 // PDLARFB in Alg. 4), fused with the first product of the next block's
-// update, on FP64 MFMA (v_mfma_f64_16x16x4f64).
+// update, on FP64 MFMA (v_mfma_f64_16x16x4f64) for an FP64 matrix and on FP32
+// MFMA (v_mfma_f32_16x16x4f32) for an FP32 matrix (the mixed-precision form:
+// reflectors formed in FP64, stored and applied in FP32).
 //
 // With the compact WY form Q~ = I - V T V^T the update is A2 -= V (T^T V^T A2).
 // The factor W' = T^T V^T A2 of block i is known before this pass (it was
@@ -10,10 +12,11 @@
 //     W_{i+1}(:, tile columns) += V_{i+1}^T tile            (K = tile rows)
 // where V_{i+1} are the next panel's reflectors (factored before this pass).
 // Each element of A2 is read and written once per block.  The updated tile
-// stays in the MFMA accumulator layout (lane l, element e: row l/16 + 4e),
-// which is exactly the B-operand layout the second product needs when the
-// reduction index of the 4-wide chunk e is taken as rows {g + 4e} (g = l/16),
-// so no data moves between the two products.
+// stays in the MFMA accumulator layout (lane l, element e: row acc_row(l/16, e),
+// l/16 + 4e for FP64, 4(l/16) + e for FP32), which is exactly the B-operand
+// layout the second product needs when the reduction index of the 4-wide
+// chunk e is taken as the rows {acc_row(g, e) : g = 0..3}, so no data moves
+// between the two products.
 //
 // Grid: x = 64-column strips (one 16-column slab per wave), y = row splits;
 // each workgroup walks its rows in 64-row tiles and keeps its W_{i+1} slab in
@@ -34,16 +37,30 @@ constexpr int TR = 32;  // rows per tile
 //         swz(r) = ((r >> 1) & 15) | ((r & 1) << 4)
 RQ_DEV int swz_n(int r) { return ((r >> 1) & 15) | ((r & 1) << 4); }
 
-template <int BBM>
-__global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
-    int m, double* __restrict__ a, long long lda, int i, int bbu, int bbn,
+template <typename T>
+struct TrailMfma;
+template <>
+struct TrailMfma<double> {
+  typedef v4d acc_t;
+  static RQ_DEV acc_t run(double a, double b, acc_t c) { return mfma_f64(a, b, c); }
+};
+template <>
+struct TrailMfma<float> {
+  typedef v4f acc_t;
+  static RQ_DEV acc_t run(float a, float b, acc_t c) { return mfma_f32(a, b, c); }
+};
+
+template <typename T, int BBM>
+__global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail(
+    int m, T* __restrict__ a, long long lda, int i, int bbu, int bbn,
     const double* __restrict__ wp, long long ldw, int w0, int c_begin, int c_end,
-    double* __restrict__ wpart, int rows_per_split) {
+    T* __restrict__ wpart, int rows_per_split) {
   static_assert(BBM % 32 == 0, "block width must be a multiple of 32");
+  typedef typename TrailMfma<T>::acc_t acc_t;
   constexpr int QS = TT / TR;       // reflector columns staged per pass of the block
   constexpr int NQ = BBM / QS;      // reflector values staged per thread and matrix
-  __shared__ double sVuT[BBM * TR];
-  __shared__ double sVn[TR * BBM];
+  __shared__ T sVuT[BBM * TR];
+  __shared__ T sVn[TR * BBM];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr16 = lane & 15, lg = lane >> 4;
@@ -56,21 +73,21 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
   // Loads below are unconditional from clamped (always valid) addresses and
   // masked afterwards: a load under a branch costs a full memory round trip.
   const int cols = colok ? col : c_begin;  // a valid column for masked lanes
-  double bw[BBM / 4];
+  T bw[BBM / 4];
 #pragma unroll
   for (int kq = 0; kq < BBM / 4; ++kq) {
     const int q = 4 * kq + lg;
     const double v = (bbu > 0) ? wp[(long long)(cols - w0) * ldw + (q < bbu ? q : 0)] : 0.0;
-    bw[kq] = (colok && q < bbu) ? -v : 0.0;
+    bw[kq] = (colok && q < bbu) ? (T)(-v) : T(0);
   }
-  v4d acc[BBM / 16];
+  acc_t acc[BBM / 16];
 #pragma unroll
-  for (int qb = 0; qb < BBM / 16; ++qb) acc[qb] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int qb = 0; qb < BBM / 16; ++qb) acc[qb] = acc_t{0, 0, 0, 0};
 
-  double* acol = a + (long long)cols * lda;
+  T* acol = a + (long long)cols * lda;
   // this thread's share of a tile's reflector rows: row rr, columns q0 + QS*j
   const int rr = tid % TR, q0 = tid / TR;
-  double pu[NQ], pn[NQ];
+  T pu[NQ], pn[NQ];
   // raw values only; the unit-lower-trapezoidal mask is applied when staging
   auto fetch_v = [&](int r0) {
     const int r = r0 + rr;
@@ -87,17 +104,17 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
   // the staged reflector rows are zero; those rows (clamped to m-1) and the
   // columns past c_end (clamped to c_begin) only feed results that are never
   // stored, so no masking is needed.
-  auto fetch_a = [&](int r0, v4d* dd) {
+  auto fetch_a = [&](int r0, acc_t* dd) {
 #pragma unroll
     for (int b = 0; b < TR / 16; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = r0 + 16 * b + acc_row<double>(lg, e);
+        const int row = r0 + 16 * b + acc_row<T>(lg, e);
         dd[b][e] = acol[row < m ? row : m - 1];
       }
   };
 
-  v4d d[TR / 16], dn[TR / 16];
+  acc_t d[TR / 16], dn[TR / 16];
   fetch_v(ri0);
   fetch_a(ri0, d);
   for (int r0 = ri0; r0 < ri1; r0 += TR) {
@@ -111,12 +128,12 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
 #pragma unroll
       for (int j = 0; j < NQ; ++j) {
         const int q = q0 + QS * j;
-        double vu = (du == q) ? 1.0 : 0.0;
+        T vu = (du == q) ? T(1) : T(0);
         vu = (du > q) ? pu[j] : vu;
-        vu = (rin & (q < bbu)) ? vu : 0.0;
-        double vn = (dv == q) ? 1.0 : 0.0;
+        vu = (rin & (q < bbu)) ? vu : T(0);
+        T vn = (dv == q) ? T(1) : T(0);
         vn = (dv > q) ? pn[j] : vn;
-        vn = (rin & (q < bbn)) ? vn : 0.0;
+        vn = (rin & (q < bbn)) ? vn : T(0);
         sVuT[q * TR + (rr ^ ((q & 1) << 4))] = vu;
         sVn[rr * BBM + (q ^ swz_n(rr))] = vn;
       }
@@ -135,15 +152,15 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
         const int q = 4 * kq + lg;
 #pragma unroll
         for (int b = 0; b < TR / 16; ++b) {
-          const double av = sVuT[q * TR + ((16 * b + lr16) ^ ((q & 1) << 4))];
-          d[b] = mfma_f64(av, bw[kq], d[b]);
+          const T av = sVuT[q * TR + ((16 * b + lr16) ^ ((q & 1) << 4))];
+          d[b] = TrailMfma<T>::run(av, bw[kq], d[b]);
         }
       }
 #pragma unroll
       for (int b = 0; b < TR / 16; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = r0 + 16 * b + acc_row<double>(lg, e);
+          const int row = r0 + 16 * b + acc_row<T>(lg, e);
           if (colok & (row < ri1)) acol[row] = d[b][e];
         }
     }
@@ -152,11 +169,11 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
       for (int b = 0; b < TR / 16; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int r = 16 * b + acc_row<double>(lg, e);
+          const int r = 16 * b + acc_row<T>(lg, e);
 #pragma unroll
           for (int qb = 0; qb < BBM / 16; ++qb) {
-            const double av = sVn[r * BBM + ((16 * qb + lr16) ^ swz_n(r))];
-            acc[qb] = mfma_f64(av, d[b][e], acc[qb]);
+            const T av = sVn[r * BBM + ((16 * qb + lr16) ^ swz_n(r))];
+            acc[qb] = TrailMfma<T>::run(av, d[b][e], acc[qb]);
           }
         }
     }
@@ -168,12 +185,12 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail_f64(
   }
 
   if (bbn > 0 && colok) {
-    double* out = wpart + ((long long)blockIdx.y * (c_end - c_begin) + (col - c_begin)) * bbn;
+    T* out = wpart + ((long long)blockIdx.y * (c_end - c_begin) + (col - c_begin)) * bbn;
 #pragma unroll
     for (int qb = 0; qb < BBM / 16; ++qb)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int q = 16 * qb + acc_row<double>(lg, e);
+        const int q = 16 * qb + acc_row<T>(lg, e);
         if (q < bbn) out[q] = acc[qb][e];
       }
   }
@@ -191,9 +208,10 @@ TrailPlan trail_plan(int m_rows, int ncols) {
   return p;
 }
 
-int launch_trail_f64(hipStream_t s, int m, double* a, long long lda, int i, int bbu, int bbn,
-                     const double* wp, long long ldw, int w0, int c_begin, int c_end,
-                     double* wpart, int nsplit, int* nsp_out) {
+template <typename T>
+int launch_trail(hipStream_t s, int m, T* a, long long lda, int i, int bbu, int bbn,
+                 const double* wp, long long ldw, int w0, int c_begin, int c_end, T* wpart,
+                 int nsplit, int* nsp_out) {
   const int ncols = c_end - c_begin;
   *nsp_out = 0;
   if (ncols <= 0 || (bbu <= 0 && bbn <= 0)) return RQ_OK;
@@ -204,13 +222,13 @@ int launch_trail_f64(hipStream_t s, int m, double* a, long long lda, int i, int 
   dim3 grid((ncols + 63) / 64, nsp);
   const int bbm = bbu > bbn ? bbu : bbn;
   if (bbm <= 32)
-    hipLaunchKernelGGL(k_trail_f64<32>, grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw, w0,
+    hipLaunchKernelGGL((k_trail<T, 32>), grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw, w0,
                        c_begin, c_end, wpart, rps);
   else if (bbm <= 64)
-    hipLaunchKernelGGL(k_trail_f64<64>, grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw, w0,
+    hipLaunchKernelGGL((k_trail<T, 64>), grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw, w0,
                        c_begin, c_end, wpart, rps);
   else if (bbm <= 128)
-    hipLaunchKernelGGL(k_trail_f64<128>, grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw,
+    hipLaunchKernelGGL((k_trail<T, 128>), grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw,
                        w0, c_begin, c_end, wpart, rps);
   else
     return RQ_ERR_LIMIT;
@@ -218,5 +236,9 @@ int launch_trail_f64(hipStream_t s, int m, double* a, long long lda, int i, int 
   *nsp_out = nsp;  // number of partial sums written
   return RQ_OK;
 }
+template int launch_trail<double>(hipStream_t, int, double*, long long, int, int, int,
+                                  const double*, long long, int, int, int, double*, int, int*);
+template int launch_trail<float>(hipStream_t, int, float*, long long, int, int, int,
+                                 const double*, long long, int, int, int, float*, int, int*);
 
 }  // namespace rq

@@ -42,17 +42,23 @@ def test_argument_checks_without_gpu():
     import paper_1804_05138_amd as rq
     lib = rq.load_library()
     out = ctypes.c_size_t()
-    prm = rq.Params(32, 8, 0, rq.F64, 0)
+    prm = rq.Params(32, 8, 0, rq.F64, rq.F64, 0)
     assert lib.rqrcp_workspace_size(100, 80, 20, ctypes.byref(prm), ctypes.byref(out)) == 0
     assert out.value > 0
     assert lib.rqrcp_workspace_size(0, 80, 20, ctypes.byref(prm), ctypes.byref(out)) == -1
     assert lib.rqrcp_workspace_size(100, 0, 20, ctypes.byref(prm), ctypes.byref(out)) == -2
     assert lib.rqrcp_workspace_size(100, 80, 81, ctypes.byref(prm), ctypes.byref(out)) == -3
     assert lib.rqrcp_workspace_size(100, 80, 0, ctypes.byref(prm), ctypes.byref(out)) == -3
-    bad = rq.Params(0, 8, 0, rq.F64, 0)
+    bad = rq.Params(0, 8, 0, rq.F64, rq.F64, 0)
     assert lib.rqrcp_workspace_size(100, 80, 20, ctypes.byref(bad), ctypes.byref(out)) == -4
     assert lib.rqrcp_factor(None, 10, 10, 5, ctypes.byref(prm), None, 10, None, None, None, 40,
                             None, None, 0) == -1
+    for bad_types in ((7, rq.F64), (rq.F64, rq.F32), (rq.F32, 9)):
+        bp = rq.Params(32, 8, 0, bad_types[0], bad_types[1], 0)
+        assert lib.rqrcp_workspace_size(100, 80, 20, ctypes.byref(bp), ctypes.byref(out)) == -4
+    for good in ((rq.F32, rq.F64), (rq.F32, rq.BF16), (rq.F32, rq.F8E4M3), (rq.F64, rq.BF16)):
+        gp = rq.Params(32, 8, 0, good[0], good[1], 0)
+        assert lib.rqrcp_workspace_size(100, 80, 20, ctypes.byref(gp), ctypes.byref(out)) == 0
     sw = ctypes.c_size_t()
     assert lib.srqr_workspace_size(100, 80, 20, ctypes.byref(prm), 16, 0, ctypes.byref(sw)) == 0
     assert sw.value > 0

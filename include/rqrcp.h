@@ -173,6 +173,29 @@ int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params *prm, doub
               int32_t *jpvt, double *tau, const double *B, int ldb, double *g2_out,
               int32_t *nswaps_out, int32_t *info, void *ws, size_t ws_bytes);
 
+/* ---- Backward of the truncated factorization with frozen pivots ----
+ * The paper differentiates nothing; this is the adjoint of the map
+ * A -> (Q1, R~), R~ = [R11 R12] (k x n, pivot order), A Pi ~ Q1 R~ (Section I-A),
+ * with Pi held fixed.  Its pieces are R12 = Q1^T A2 and the QR A1 = Q1 R11 of
+ * the k pivoted columns:
+ *   A2_bar = Q1 R12_bar;  Q1_bar' = Q1_bar + A2 R12_bar^T;
+ *   M = R11 R11_bar^T - Q1_bar'^T Q1;
+ *   A1_bar = (Q1_bar' + Q1 (tril(M) + tril(M,-1)^T)) R11^-T;
+ *   A_bar(:, jpvt[j]) = [A1_bar A2_bar](:, j).
+ * Q1 and every block's T are recomputed from (V, tau); products on MFMA in
+ * the storage precision a_type (RQRCP_F64 or RQRCP_F32).
+ *  A      (in) the original m x n matrix (lda), unpivoted.
+ *  AF     (in) its factorization from rqrcp_factor (ldaf, same a_type), tau, jpvt.
+ *  dQ1    (in) m x k cotangent of Q1 (ldq), or NULL for zero.
+ *  dR     (in) k x n cotangent of R~ in pivot order (ldr), or NULL for zero.
+ *  dA     (out) m x n (ldda), original column order.
+ * Limits: k <= 1024. */
+int rqrcp_backward_workspace_size(int m, int n, int k, int b, int a_type, size_t *bytes);
+int rqrcp_backward(rqrcp_handle h, int m, int n, int k, int b, int a_type, const void *A, int lda,
+                   const void *AF, int ldaf, const double *tau, const int32_t *jpvt,
+                   const void *dQ1, int ldq, const void *dR, int ldr, void *dA, int ldda,
+                   void *ws, size_t ws_bytes);
+
 /* Synchronizes the handle's stream and returns RQRCP_ERR_BARRIER if a
  * persistent kernel reported a barrier timeout since the last check (and
  * clears the flag), RQRCP_ERR_HIP on a HIP error, else 0.  `ws` is the

@@ -38,7 +38,7 @@ EXPORTS = (
     "rqrcp_create", "rqrcp_destroy", "rqrcp_set_stream", "rqrcp_workspace_size",
     "rqrcp_limits", "rqrcp_gaussian", "rqrcp_sketch", "rqrcp_factor", "rqrcp_form_q",
     "rqrcp_check", "rqrcp_status_string", "rqrcp_set_timing", "rqrcp_read_timing",
-    "srqr_workspace_size", "srqr_swap",
+    "srqr_workspace_size", "srqr_swap", "rqrcp_backward_workspace_size", "rqrcp_backward",
 )
 PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other")
 
@@ -74,6 +74,9 @@ def load_library(path: str = LIB_PATH):
         "rqrcp_form_q": (i, [vp, i, i, i, i, vp, i, vp, vp, i, vp, sz]),
         "rqrcp_check": (i, [vp, vp]),
         "srqr_workspace_size": (i, [i, i, i, P(Params), i, ctypes.c_uint, P(sz)]),
+        "rqrcp_backward_workspace_size": (i, [i, i, i, i, i, P(sz)]),
+        "rqrcp_backward": (i, [vp, i, i, i, i, i, vp, i, vp, i, vp, vp, vp, i, vp, i, vp, i,
+                               vp, sz]),
         "srqr_swap": (i, [vp, i, i, i, P(Params), ctypes.c_double, i, i, ctypes.c_uint,
                           vp, i, vp, i, vp, vp, vp, i, vp, vp, vp, vp, sz]),
         "rqrcp_status_string": (ctypes.c_char_p, [i]),
@@ -357,6 +360,76 @@ def srqr(a0, l, b, p, g, seed=0, *, d=16, exact=False, max_swaps=-1, sketch_b=No
                          ws.numel()), "srqr_swap")
     _check(lib.rqrcp_check(handle(), _ptr(ws)), "rqrcp_check")
     return SRQR(f.a, f.jpvt, tau, g2, ns, info)
+
+
+def backward(a, fact, dq1=None, dr=None):
+    """dL/dA of the frozen-pivot factorization ``fact`` of ``a`` (rqrcp_backward).
+
+    dq1: m x k cotangent of Q1, dr: k x n cotangent of [R11 R12] (pivot order);
+    either may be None (zero).  Returns dA (m x n, original column order).
+    """
+    torch = _torch()
+    a = colmajor(a, fact.a.dtype)
+    m, n = a.shape
+    k, b = fact.k, fact.block
+    at = _a_type(a.dtype)
+    dq1 = colmajor(dq1, a.dtype) if dq1 is not None else None
+    dr = colmajor(dr, a.dtype) if dr is not None else None
+    da = empty_colmajor(m, n, a.dtype, a.device)
+    lib = load_library()
+    nb = ctypes.c_size_t()
+    _check(lib.rqrcp_backward_workspace_size(m, n, k, b, at, ctypes.byref(nb)),
+           "rqrcp_backward_workspace_size")
+    ws = workspace(nb.value, a.device)
+    _check(lib.rqrcp_backward(handle(), m, n, k, b, at, _ptr(a), _ld(a), _ptr(fact.a),
+                              _ld(fact.a), _ptr(fact.tau), _ptr(fact.jpvt), _ptr(dq1),
+                              _ld(dq1) if dq1 is not None else m, _ptr(dr),
+                              _ld(dr) if dr is not None else k, _ptr(da), _ld(da), _ptr(ws),
+                              ws.numel()), "rqrcp_backward")
+    return da
+
+
+_FN = None
+
+
+def _function():
+    """torch.autograd.Function over rqrcp_factor / rqrcp_form_q / rqrcp_backward."""
+    global _FN
+    if _FN is not None:
+        return _FN
+    torch = _torch()
+
+    class RQRCPFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, a, k, b, p, seed, jpvt, sketch_type):
+            f = factor(a.detach(), k, b, p, seed, jpvt=jpvt, sketch_type=sketch_type)
+            q1 = form_q(f.a, f.tau, k, b)
+            r = colmajor(torch.triu(f.a[:k]))
+            ctx.save_for_backward(a.detach(), f.a, f.tau, f.jpvt)
+            ctx.k, ctx.b = k, b
+            jp = f.jpvt.clone()
+            ctx.mark_non_differentiable(jp)
+            return q1, r, jp
+
+        @staticmethod
+        def backward(ctx, dq1, dr, _djp):
+            a, af, tau, jp = ctx.saved_tensors
+            fact = Factorization(af, jp, tau, None, None, ctx.k, ctx.b)
+            da = backward(a, fact, dq1, dr)
+            return da.to(a.dtype), None, None, None, None, None, None
+
+    _FN = RQRCPFunction
+    return _FN
+
+
+def rqrcp(a, k, b, p, seed=0, *, jpvt=None, sketch_type="f64"):
+    """Differentiable truncated RQRCP: returns (Q1, R~, jpvt) with A Pi ~ Q1 R~.
+
+    R~ = [R11 R12] is k x n in pivot order; the gradient treats the pivots as
+    fixed (they are piecewise constant in A).  Runs in the dtype of ``a``
+    (float64, or float32 for the mixed-precision form).
+    """
+    return _function().apply(a, k, b, p, seed, jpvt, sketch_type)
 
 
 def set_timing(enable: bool):

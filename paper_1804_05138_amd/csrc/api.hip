@@ -612,6 +612,52 @@ int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, int a_type, const void* A,
                         (double*)work);
 }
 
+int rqrcp_backward_workspace_size(int m, int n, int k, int b, int a_type, size_t* bytes) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (k < 1 || k > std::min(m, n)) return -3;
+  if (b < 1 || b > MAX_B) return -4;
+  if (a_type != RQRCP_F64 && a_type != RQRCP_F32) return -5;
+  if (!bytes) return -6;
+  *bytes = HEADER + backward_layout(m, n, k, b, elem_size(a_type)).total;
+  return 0;
+}
+
+int rqrcp_backward(rqrcp_handle h, int m, int n, int k, int b, int a_type, const void* A, int lda,
+                   const void* AF, int ldaf, const double* tau, const int32_t* jpvt,
+                   const void* dQ1, int ldq, const void* dR, int ldr, void* dA, int ldda,
+                   void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  if (b < 1 || b > MAX_B) return -5;
+  if (a_type != RQRCP_F64 && a_type != RQRCP_F32) return -6;
+  if (!A) return -7;
+  if (lda < m) return -8;
+  if (!AF) return -9;
+  if (ldaf < m) return -10;
+  if (!tau) return -11;
+  if (!jpvt) return -12;
+  if (dQ1 && ldq < m) return -14;
+  if (dR && ldr < k) return -16;
+  if (!dA) return -17;
+  if (ldda < m) return -18;
+  if (k > 1024) return RQRCP_ERR_LIMIT;
+  size_t need = 0;
+  int rc = rqrcp_backward_workspace_size(m, n, k, b, a_type, &need);
+  if (rc) return rc;
+  if (!ws || ws_bytes < need) return RQRCP_ERR_WORKSPACE;
+  char* w = (char*)ws + HEADER;
+  if (a_type == RQRCP_F32)
+    return backward<float>(h->stream, m, n, k, b, (const float*)A, lda, (const float*)AF, ldaf,
+                           tau, jpvt, (const float*)dQ1, ldq, (const float*)dR, ldr, (float*)dA,
+                           ldda, w);
+  return backward<double>(h->stream, m, n, k, b, (const double*)A, lda, (const double*)AF, ldaf,
+                          tau, jpvt, (const double*)dQ1, ldq, (const double*)dR, ldr, (double*)dA,
+                          ldda, w);
+}
+
 int rqrcp_check(rqrcp_handle h, void* ws) {
   if (!h) return -1;
   if (hipStreamSynchronize(h->stream) != hipSuccess) return RQRCP_ERR_HIP;

@@ -21,4 +21,14 @@ template <typename T>
 int form_q(hipStream_t s, int m, int k, int b, const T* a, long long lda, const double* tau, T* q,
            long long ldq, T* work);
 
+// Frozen-pivot adjoint (k_backward.hip): byte offsets of its workspace.
+struct BackwardLayout {
+  size_t q1, a2, qb, g, r11, rinv, mm, formq, total;
+};
+BackwardLayout backward_layout(int m, int n, int k, int b, size_t es);
+template <typename T>
+int backward(hipStream_t s, int m, int n, int k, int b, const T* a, long long lda, const T* af,
+             long long ldaf, const double* tau, const int* jpvt, const T* dq1, long long ldq,
+             const T* dr, long long ldr, T* da, long long ldda, char* ws);
+
 }  // namespace rq

@@ -196,6 +196,49 @@ int rqrcp_backward(rqrcp_handle h, int m, int n, int k, int b, int a_type, const
                    const void *dQ1, int ldq, const void *dR, int ldr, void *dA, int ldda,
                    void *ws, size_t ws_bytes);
 
+/* ---- Batched RQRCP of many small, uneven FP32 matrices ----
+ * One persistent launch: each workgroup factors one problem at a time (Alg. 2
+ * with FP64 sketch, reflectors and sample update, FP32 storage and trailing
+ * update) and takes the next problem from a work queue in the workspace, so
+ * the call allocates nothing, synchronizes nothing and can be captured in a
+ * HIP graph.  Problem j draws its Omega from Philox(prm->seed, stream j + 1).
+ * Descriptors are device data; offsets count elements of the pools. */
+typedef struct {
+  int64_t a_off;    /* A_j at A_pool + a_off: m x n FP32, column-major, leading dim lda */
+  int64_t b_off;    /* final sketch at B_pool + b_off: (b+p) x n FP64, leading dim b+p */
+  int64_t jpvt_off; /* n ints at jpvt_pool + jpvt_off */
+  int64_t tau_off;  /* k doubles at tau_pool + tau_off */
+  int32_t m, n, k, lda;
+} rqrcp_problem;
+
+/* Limits of the batched kernel (host outputs): m <= max_m, (b+p) n <= max_ln,
+ * n <= 1024, b <= max_b, b + p <= max_l. */
+int rqrcp_batched_limits(int *max_m, int *max_ln, int *max_b, int *max_l);
+int rqrcp_batched_workspace_size(size_t *bytes);
+/* Factor `batch` problems in place (A_j -> R, V, R22 in LAPACK storage).
+ * prm: a_type = RQRCP_F32, sketch_type = RQRCP_F64, b, p, seed.  *_elems are the
+ * pool sizes in elements; a problem whose descriptor does not fit the kernel's
+ * limits or the pools is skipped with info[j] = -1.  info[j] otherwise as in
+ * rqrcp_factor.  The kernel variant comes from the handle's tuning table
+ * (rqrcp_autotune_batched), default variant 0. */
+int rqrcp_factor_batched(rqrcp_handle h, int batch, const rqrcp_problem *probs,
+                         const rqrcp_params *prm, float *A_pool, int64_t a_elems,
+                         int32_t *jpvt_pool, int64_t jpvt_elems, double *tau_pool,
+                         int64_t tau_elems, double *B_pool, int64_t b_elems, int32_t *info,
+                         void *ws, size_t ws_bytes);
+/* Autotuner: for every kernel variant, restores A_pool from A_orig (a device
+ * copy of the inputs with the same layout, a_elems floats), runs the variant
+ * twice and times the second run with HIP events; stores the fastest in the
+ * handle's table for (b, b+p) and finally runs it once more, so the outputs
+ * hold its factorization.  Synchronizes.  best_variant and ms_per_variant
+ * (host, may be NULL; at most 8 entries) report the measurements. */
+int rqrcp_autotune_batched(rqrcp_handle h, int batch, const rqrcp_problem *probs,
+                           const rqrcp_params *prm, float *A_pool, int64_t a_elems,
+                           int32_t *jpvt_pool, int64_t jpvt_elems, double *tau_pool,
+                           int64_t tau_elems, double *B_pool, int64_t b_elems, int32_t *info,
+                           void *ws, size_t ws_bytes, const float *A_orig, int *best_variant,
+                           float *ms_per_variant);
+
 /* Synchronizes the handle's stream and returns RQRCP_ERR_BARRIER if a
  * persistent kernel reported a barrier timeout since the last check (and
  * clears the flag), RQRCP_ERR_HIP on a HIP error, else 0.  `ws` is the

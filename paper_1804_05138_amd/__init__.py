@@ -39,6 +39,8 @@ EXPORTS = (
     "rqrcp_limits", "rqrcp_gaussian", "rqrcp_sketch", "rqrcp_factor", "rqrcp_form_q",
     "rqrcp_check", "rqrcp_status_string", "rqrcp_set_timing", "rqrcp_read_timing",
     "srqr_workspace_size", "srqr_swap", "rqrcp_backward_workspace_size", "rqrcp_backward",
+    "rqrcp_batched_limits", "rqrcp_batched_workspace_size", "rqrcp_factor_batched",
+    "rqrcp_autotune_batched",
 )
 PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other")
 
@@ -61,6 +63,7 @@ def load_library(path: str = LIB_PATH):
         raise RuntimeError(f"librqrcp.so not built ({path}); run paper_1804_05138_amd/build.py")
     lib = ctypes.CDLL(path)
     vp, i, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
+    i64 = ctypes.c_int64
     P = ctypes.POINTER
     sig = {
         "rqrcp_create": (i, [P(vp), vp]),
@@ -75,6 +78,12 @@ def load_library(path: str = LIB_PATH):
         "rqrcp_check": (i, [vp, vp]),
         "srqr_workspace_size": (i, [i, i, i, P(Params), i, ctypes.c_uint, P(sz)]),
         "rqrcp_backward_workspace_size": (i, [i, i, i, i, i, P(sz)]),
+        "rqrcp_batched_limits": (i, [P(i), P(i), P(i), P(i)]),
+        "rqrcp_batched_workspace_size": (i, [P(sz)]),
+        "rqrcp_factor_batched": (i, [vp, i, vp, P(Params), vp, i64, vp, i64, vp, i64, vp, i64,
+                                     vp, vp, sz]),
+        "rqrcp_autotune_batched": (i, [vp, i, vp, P(Params), vp, i64, vp, i64, vp, i64, vp, i64,
+                                       vp, vp, sz, vp, P(i), P(ctypes.c_float)]),
         "rqrcp_backward": (i, [vp, i, i, i, i, i, vp, i, vp, i, vp, vp, vp, i, vp, i, vp, i,
                                vp, sz]),
         "srqr_swap": (i, [vp, i, i, i, P(Params), ctypes.c_double, i, i, ctypes.c_uint,
@@ -430,6 +439,87 @@ def rqrcp(a, k, b, p, seed=0, *, jpvt=None, sketch_type="f64"):
     (float64, or float32 for the mixed-precision form).
     """
     return _function().apply(a, k, b, p, seed, jpvt, sketch_type)
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+# numpy layout of rqrcp_problem (include/rqrcp.h)
+PROBLEM_FIELDS = [("a_off", "<i8"), ("b_off", "<i8"), ("jpvt_off", "<i8"), ("tau_off", "<i8"),
+                  ("m", "<i4"), ("n", "<i4"), ("k", "<i4"), ("lda", "<i4")]
+
+
+@dataclass
+class Batch:
+    """Device pools and descriptors of a batch of column-major FP32 problems."""
+    desc: object     # uint8 device tensor holding rqrcp_problem[batch]
+    a: object        # float32 pool (problems back to back, lda = m)
+    jpvt: object     # int32 pool
+    tau: object      # float64 pool
+    b: object        # float64 pool (final sketches, ld = b + p)
+    info: object     # int32 (batch,)
+    ws: object       # uint8 workspace
+    shapes: list     # (m, n, k) per problem
+    offsets: object  # numpy structured array of the descriptors
+    l: int
+
+
+def make_batch(shapes, l, device="cuda"):
+    """Pools and descriptors for problems of the given (m, n, k) shapes."""
+    import numpy as np
+    torch = _torch()
+    recs = np.zeros(len(shapes), dtype=np.dtype(PROBLEM_FIELDS))
+    ao = bo = jo = to = 0
+    for j, (m, n, k) in enumerate(shapes):
+        recs[j] = (ao, bo, jo, to, m, n, k, m)
+        ao += m * n
+        bo += l * n
+        jo += n
+        to += k
+    desc = torch.from_numpy(recs.view(np.uint8).copy()).to(device)
+    nb = ctypes.c_size_t()
+    _check(load_library().rqrcp_batched_workspace_size(ctypes.byref(nb)),
+           "rqrcp_batched_workspace_size")
+    return Batch(desc, torch.zeros(max(ao, 1), dtype=torch.float32, device=device),
+                 torch.zeros(max(jo, 1), dtype=torch.int32, device=device),
+                 torch.zeros(max(to, 1), dtype=torch.float64, device=device),
+                 torch.zeros(max(bo, 1), dtype=torch.float64, device=device),
+                 torch.zeros(len(shapes), dtype=torch.int32, device=device),
+                 workspace(nb.value, device), list(shapes), recs, l)
+
+
+def factor_batched(batch: Batch, b, p, seed=0):
+    """rqrcp_factor_batched on the pools of ``batch`` (in place; no sync, no
+    allocation, so it can be captured in a graph)."""
+    prm = Params(b, p, seed, F32, F64, 0)
+    _check(load_library().rqrcp_factor_batched(
+        handle(), len(batch.shapes), _ptr(batch.desc), ctypes.byref(prm), _ptr(batch.a),
+        batch.a.numel(), _ptr(batch.jpvt), batch.jpvt.numel(), _ptr(batch.tau),
+        batch.tau.numel(), _ptr(batch.b), batch.b.numel(), _ptr(batch.info), _ptr(batch.ws),
+        batch.ws.numel()), "rqrcp_factor_batched")
+
+
+def autotune_batched(batch: Batch, a_orig, b, p, seed=0):
+    """rqrcp_autotune_batched: (best variant, ms per variant); outputs are left
+    holding the best variant's factorization of ``a_orig``."""
+    prm = Params(b, p, seed, F32, F64, 0)
+    best = ctypes.c_int()
+    ms = (ctypes.c_float * 8)()
+    _check(load_library().rqrcp_autotune_batched(
+        handle(), len(batch.shapes), _ptr(batch.desc), ctypes.byref(prm), _ptr(batch.a),
+        batch.a.numel(), _ptr(batch.jpvt), batch.jpvt.numel(), _ptr(batch.tau),
+        batch.tau.numel(), _ptr(batch.b), batch.b.numel(), _ptr(batch.info), _ptr(batch.ws),
+        batch.ws.numel(), _ptr(a_orig), ctypes.byref(best), ms), "rqrcp_autotune_batched")
+    return best.value, [ms[v] for v in range(2)]
+
+
+def batched_limits():
+    lib = load_library()
+    mm, ml, mb, mx = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    lib.rqrcp_batched_limits(ctypes.byref(mm), ctypes.byref(ml), ctypes.byref(mb),
+                             ctypes.byref(mx))
+    return mm.value, ml.value, mb.value, mx.value
 
 
 def set_timing(enable: bool):

@@ -36,6 +36,8 @@ struct rqrcp_ctx {
     double flops, bytes;
   };
   bool timing = false;
+  // batched kernel variant per (b, b + p), -1 = not tuned (autotuner table)
+  int batched_variant[17][33];
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
   double ms[RQRCP_NPHASES] = {};
@@ -360,6 +362,8 @@ int rqrcp_create(rqrcp_handle* h, void* stream) {
   if (!c) return RQRCP_ERR_HIP;
   c->stream = (hipStream_t)stream;
   c->device = dev;
+  for (auto& row : c->batched_variant)
+    for (int& v : row) v = -1;
   *h = c;
   return 0;
 }
@@ -656,6 +660,102 @@ int rqrcp_backward(rqrcp_handle h, int m, int n, int k, int b, int a_type, const
   return backward<double>(h->stream, m, n, k, b, (const double*)A, lda, (const double*)AF, ldaf,
                           tau, jpvt, (const double*)dQ1, ldq, (const double*)dR, ldr, (double*)dA,
                           ldda, w);
+}
+
+int rqrcp_batched_limits(int* max_m, int* max_ln, int* max_b, int* max_l) {
+  return batched_max(max_m, max_ln, max_b, max_l);
+}
+
+int rqrcp_batched_workspace_size(size_t* bytes) {
+  if (!bytes) return -1;
+  *bytes = 256;
+  return 0;
+}
+
+static int batched_checks(rqrcp_handle h, int batch, const rqrcp_problem* probs,
+                          const rqrcp_params* prm, float* A_pool, int32_t* jpvt_pool,
+                          double* tau_pool, double* B_pool, int32_t* info, void* ws,
+                          size_t ws_bytes) {
+  if (!h) return -1;
+  if (batch < 0) return -2;
+  if (!probs && batch > 0) return -3;
+  int mb = 0, ml = 0;
+  batched_max(nullptr, nullptr, &mb, &ml);
+  if (!prm || prm->b < 1 || prm->b > mb || prm->p < 0 || prm->b + prm->p > ml) return -4;
+  if (prm->a_type != RQRCP_F32 || prm->sketch_type != RQRCP_F64) return RQRCP_ERR_UNSUPPORTED;
+  if (!A_pool) return -5;
+  if (!jpvt_pool) return -7;
+  if (!tau_pool) return -9;
+  if (!B_pool) return -11;
+  if (!info) return -13;
+  if (!ws || ws_bytes < 256) return RQRCP_ERR_WORKSPACE;
+  return 0;
+}
+
+int rqrcp_factor_batched(rqrcp_handle h, int batch, const rqrcp_problem* probs,
+                         const rqrcp_params* prm, float* A_pool, int64_t a_elems,
+                         int32_t* jpvt_pool, int64_t jpvt_elems, double* tau_pool,
+                         int64_t tau_elems, double* B_pool, int64_t b_elems, int32_t* info,
+                         void* ws, size_t ws_bytes) {
+  int rc = batched_checks(h, batch, probs, prm, A_pool, jpvt_pool, tau_pool, B_pool, info, ws,
+                          ws_bytes);
+  if (rc) return rc;
+  if (batch == 0) return 0;
+  const int l = prm->b + prm->p;
+  int v = h->batched_variant[prm->b][l];
+  if (v < 0) v = 0;
+  return launch_batched(h->stream, v, batch, probs, prm->b, l, prm->seed, A_pool, a_elems,
+                        jpvt_pool, jpvt_elems, tau_pool, tau_elems, B_pool, b_elems, info,
+                        (unsigned*)ws);
+}
+
+int rqrcp_autotune_batched(rqrcp_handle h, int batch, const rqrcp_problem* probs,
+                           const rqrcp_params* prm, float* A_pool, int64_t a_elems,
+                           int32_t* jpvt_pool, int64_t jpvt_elems, double* tau_pool,
+                           int64_t tau_elems, double* B_pool, int64_t b_elems, int32_t* info,
+                           void* ws, size_t ws_bytes, const float* A_orig, int* best_variant,
+                           float* ms_per_variant) {
+  int rc = batched_checks(h, batch, probs, prm, A_pool, jpvt_pool, tau_pool, B_pool, info, ws,
+                          ws_bytes);
+  if (rc) return rc;
+  if (!A_orig) return -16;
+  if (batch == 0 || a_elems <= 0) return 0;
+  const int l = prm->b + prm->p;
+  const int nv = batched_variants();
+  hipEvent_t e0 = h->event(), e1 = h->event();
+  if (!e0 || !e1) return RQRCP_ERR_HIP;
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int v = 0; v < nv; ++v) {
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first run warms up
+      RQ_HIP_CHECK(hipMemcpyAsync(A_pool, A_orig, (size_t)a_elems * sizeof(float),
+                                  hipMemcpyDeviceToDevice, h->stream));
+      RQ_HIP_CHECK(hipEventRecord(e0, h->stream));
+      rc = launch_batched(h->stream, v, batch, probs, prm->b, l, prm->seed, A_pool, a_elems,
+                          jpvt_pool, jpvt_elems, tau_pool, tau_elems, B_pool, b_elems, info,
+                          (unsigned*)ws);
+      if (rc) return rc;
+      RQ_HIP_CHECK(hipEventRecord(e1, h->stream));
+      RQ_HIP_CHECK(hipEventSynchronize(e1));
+      RQ_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    }
+    if (ms_per_variant && v < 8) ms_per_variant[v] = ms;
+    if (v == 0 || ms < best_ms) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  h->pool.push_back(e0);
+  h->pool.push_back(e1);
+  h->batched_variant[prm->b][l] = best;
+  if (best_variant) *best_variant = best;
+  // leave the outputs of the chosen variant
+  RQ_HIP_CHECK(hipMemcpyAsync(A_pool, A_orig, (size_t)a_elems * sizeof(float),
+                              hipMemcpyDeviceToDevice, h->stream));
+  return launch_batched(h->stream, best, batch, probs, prm->b, l, prm->seed, A_pool, a_elems,
+                        jpvt_pool, jpvt_elems, tau_pool, tau_elems, B_pool, b_elems, info,
+                        (unsigned*)ws);
 }
 
 int rqrcp_check(rqrcp_handle h, void* ws) {

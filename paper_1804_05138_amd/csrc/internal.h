@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/rqrcp.h"
 #include "common.h"
 
 namespace rq {
@@ -92,6 +93,15 @@ template <typename T>
 int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int bb,
                    const double* t, const T* wpart, int nsplit, double* wp, long long ldw,
                    double* bsk, long long ldb, int c0, int ncols, const int* info);
+
+// Batched RQRCP (k_batched.hip): variant v of the persistent kernel.
+int batched_variants();
+const char* batched_variant_name(int v);
+int batched_max(int* max_m, int* max_ln, int* max_b, int* max_l);
+int launch_batched(hipStream_t s, int variant, int batch, const rqrcp_problem* probs, int b, int l,
+                   uint64_t seed, float* apool, long long a_elems, int* jpool, long long j_elems,
+                   double* tpool, long long t_elems, double* bpool, long long b_elems, int* infos,
+                   unsigned* queue);
 
 // Explicit Q1 = H_0 ... H_{k-1} [I; 0] (m x k) from LAPACK storage.
 int launch_form_q(hipStream_t s, int m, int k, int b, const double* a, long long lda,

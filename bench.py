@@ -12,6 +12,18 @@ Reported: TFLOP/s of the algorithmic RQRCP flop count (flops.py), the
 roofline position of the dominant kernel (the fused trailing update, FP64
 MFMA), measured with HIP events on the library's stream, and the CPU oracle
 timed on a bounded sample of the same workload.
+
+Unless --no-extras, the same JSON line also carries, under "extras", one
+measurement of each of the other forms on its own workload (each a few
+seconds of GPU time):
+  full_rank    FP64 RQRCP of a 32768 x 8192 i.i.d. N(0,1) matrix, k = 8192
+  mixed        32768 x 32768, sigma_j = j^-2 plus N(0, (1e-6)^2) noise, k = 2048,
+               b = 128, p = 16: FP64 plain vs FP32 storage/update with FP64, BF16
+               and FP8 sketches; time and ||A Pi - Q1 R~||_F / ||A||_F of each
+  batched      4096 FP32 problems, m ~ U{64..1024}, n ~ U{64..512}, k = n/8, b = 16,
+               p = 8, sigma_j = exp(-j/(n/10)); autotuned, HIP-graph replay
+  backward     frozen-pivot adjoint of 8192 x 4096 FP32, sigma_j = 1/j, k = 256
+  srqr         srqr_swap (Alg. 3, d = 16, g = 5) after the timed factorization
 """
 from __future__ import annotations
 
@@ -78,6 +90,201 @@ def cpu_baseline(a_dev, k_sample):
                       f"{M}x{N} matrix, b={B}, p={P}: {fl:.3e} flop in {dt:.2f} s"}
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def extra_srqr(rq, a0, fact):
+    """srqr_swap (Alg. 3) on the factorization of the timed workload, l = k."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tau, g2, ns, info = rq.srqr_into(a0, fact, 5.0, seed=SEED, d=16)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"{M}x{N}, l = k = {K}, d = 16, g = 5", "ms": round(dt * 1e3, 3),
+            "g2": float(g2.item()), "nswaps": int(ns.item()), "info": int(info.item())}
+
+
+def extra_full_rank(rq, steps=2):
+    """FP64 RQRCP of a 32768 x 8192 i.i.d. N(0,1) matrix to full rank k = 8192."""
+    import torch
+    from paper_1804_05138_amd.flops import rqrcp_flops
+    from workloads import gaussian_torch
+    m, n, k, b, p = 32768, 8192, 8192, 64, 8
+    a = gaussian_torch(m, n, SEED, device="cuda")
+    dev = a.device
+    jp = torch.empty(n, dtype=torch.int32, device=dev)
+    tau = torch.empty(k, dtype=torch.float64, device=dev)
+    bs = torch.empty((n, b + p), dtype=torch.float64, device=dev).t()
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(rq.workspace_bytes(m, n, k, b, p), dtype=torch.uint8, device=dev)
+    work = a.t().clone().t()
+    rq.factor_into(work, k, b, p, SEED, jp, tau, bs, info, ws)   # warm-up
+    rq.check(ws)
+    times = []
+    for _ in range(steps):
+        work.copy_(a)
+        e0, e1 = _events()
+        e0.record()
+        rq.factor_into(work, k, b, p, SEED, jp, tau, bs, info, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    rq.check(ws)
+    ms = min(times)
+    fl = rqrcp_flops(m, n, k, b, p)
+    return {"workload": "FP64 32768x8192 i.i.d. N(0,1), k=8192, b=64, p=8",
+            "ms": round(ms, 2), "tflops": round(fl / ms / 1e9, 3),
+            "pct_fp64_mfma_peak": round(100 * fl / ms / 1e9 / PEAK_FP64_MFMA, 2)}
+
+
+def _residual(rq, a64, f, k, b):
+    """||A Pi - Q1 [R11 R12]||_F / ||A||_F, in FP64 on the GPU."""
+    import torch
+    q = rq.form_q(f.a, f.tau, k, b).double()
+    r = torch.triu(f.a[:k].double())
+    api = a64[:, f.jpvt.long()]
+    res = torch.linalg.norm(api - q @ r) / torch.linalg.norm(a64)
+    return float(res)
+
+
+def extra_mixed(rq):
+    """FP64 plain vs the mixed-precision form on the 32768^2 workload."""
+    import numpy as np
+    import torch
+    from paper_1804_05138_amd.flops import rqrcp_flops
+    from workloads import lowrank_torch, sigma_pow
+    m = n = 32768
+    k, b, p = 2048, 128, 16
+    r = 8192   # signal rank kept: the omitted tail sum_{j>8192} j^-4 is 4e-5 of the noise energy
+    a64 = lowrank_torch(m, n, sigma_pow(r, 2.0), SEED, device="cuda", noise_std=1e-6)
+    fl = rqrcp_flops(m, n, k, b, p)
+    tail = float(np.sqrt(np.sum(np.arange(k + 1, r + 1, dtype=np.float64) ** -4.0)))
+    out = {"workload": "32768x32768, sigma_j = j^-2 (rank 8192) + N(0, 1e-12), k=2048, b=128, "
+                       "p=16", "flops": fl,
+           "signal_tail_sqrt_sum_sigma2_j_gt_k": tail,
+           "noise_fro": 1e-6 * m}
+    res64 = None
+    for name, dtype, st in (("fp64", torch.float64, "f64"), ("fp32_update_f64_sketch",
+                            torch.float32, "f64"), ("fp32_update_bf16_sketch", torch.float32,
+                            "bf16"), ("fp32_update_fp8_sketch", torch.float32, "fp8")):
+        src = a64 if dtype == torch.float64 else a64.float()
+        ws = torch.empty(rq.workspace_bytes(m, n, k, b, p, 0, rq._a_type(dtype),
+                                            rq._sketch_type(st)), dtype=torch.uint8,
+                         device="cuda")
+        rq.factor(src, k, b, p, SEED, ws=ws, sketch_type=st)     # warm-up
+        work = src.t().clone().t()
+        e0, e1 = _events()
+        torch.cuda.synchronize()
+        e0.record()
+        f = rq.factor(work, k, b, p, SEED, ws=ws, inplace=True, check=False, sketch_type=st)
+        e1.record()
+        torch.cuda.synchronize()
+        rq.check(ws)
+        ms = e0.elapsed_time(e1)
+        res = _residual(rq, a64, f, k, b)
+        if name == "fp64":
+            res64 = res
+        out[name] = {"ms": round(ms, 2), "tflops": round(fl / ms / 1e9, 3), "residual": res,
+                     "residual_ratio_vs_fp64": round(res / res64, 6)}
+        del work, f, ws, src
+        torch.cuda.empty_cache()
+    out["speedup_bf16_vs_fp64"] = round(out["fp64"]["ms"] / out["fp32_update_bf16_sketch"]["ms"], 3)
+    return out
+
+
+def extra_batched(rq, count=4096, reps=3):
+    """4096 uneven FP32 problems in one persistent launch, replayed from a HIP graph."""
+    import torch
+    from paper_1804_05138_amd.flops import rqrcp_flops
+    from workloads import batch_shapes
+    b, p = 16, 8
+    shapes = batch_shapes(count, SEED)
+    bt = rq.make_batch(shapes, b + p)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(SEED * 1000003 + 41)
+    for j, (m, n, k) in enumerate(shapes):
+        r = min(m, n)
+        sig = torch.exp(-torch.arange(1, r + 1, device="cuda", dtype=torch.float64) / (n / 10.0))
+        u, _ = torch.linalg.qr(torch.randn(m, r, generator=gen, device="cuda", dtype=torch.float64))
+        v, _ = torch.linalg.qr(torch.randn(n, r, generator=gen, device="cuda", dtype=torch.float64))
+        off = int(bt.offsets[j]["a_off"])
+        bt.a[off:off + m * n].copy_(((v * sig) @ u.T).reshape(-1).float())   # column-major A
+    a0 = bt.a.clone()
+    best, ms_v = rq.autotune_batched(bt, a0, b, p, seed=SEED)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        bt.a.copy_(a0)
+        rq.factor_batched(bt, b, p, seed=SEED)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        rq.factor_batched(bt, b, p, seed=SEED)
+    times = []
+    for _ in range(reps):
+        bt.a.copy_(a0)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ok = int((bt.info == 0).sum().item())
+    ms = min(times)
+    fl = sum(rqrcp_flops(m, n, k, b, p) for m, n, k in shapes)
+    nbytes = sum(8.0 * m * n for m, n, _ in shapes)
+    return {"workload": f"{count} FP32 problems, m~U[64,1024], n~U[64,512], k=n/8, b=16, p=8",
+            "ms": round(ms, 3), "tflops": round(fl / ms / 1e9, 3),
+            "algorithmic_gbps": round(nbytes / ms / 1e6, 1),
+            "pct_hbm_peak": round(100 * nbytes / ms / 1e6 / PEAK_HBM, 2),
+            "autotuner": {"best_variant": best, "ms_per_variant": [round(x, 3) for x in ms_v]},
+            "problems_ok": ok}
+
+
+def extra_backward(rq):
+    """Forward + frozen-pivot backward of 8192 x 4096 FP32, sigma_j = 1/j, k = 256."""
+    import numpy as np
+    import torch
+    from paper_1804_05138_amd.flops import backward_flops, rqrcp_flops
+    from workloads import lowrank_torch
+    m, n, k, b, p = 8192, 4096, 256, 64, 8
+    a = lowrank_torch(m, n, 1.0 / np.arange(1, n + 1), 5, device="cuda", dtype=torch.float32)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    w = torch.randn(n, m, generator=gen, device="cuda", dtype=torch.float32).t()
+    f = rq.factor(a, k, b, p, 4)
+    dq1 = torch.randn(k, m, generator=gen, device="cuda", dtype=torch.float32).t()
+    dr = torch.randn(n, k, generator=gen, device="cuda", dtype=torch.float32).t()
+    rq.backward(a, f, dq1, dr)     # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        e0, e1 = _events()
+        e0.record()
+        rq.backward(a, f, dq1, dr)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = min(times)
+    fl = backward_flops(m, n, k, b)
+    e0, e1 = _events()
+    e0.record()
+    rq.factor(a, k, b, p, 4, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    fms = e0.elapsed_time(e1)
+    del w
+    return {"workload": "FP32 8192x4096, sigma_j = 1/j, k=256, b=64, p=8",
+            "backward_ms": round(ms, 3), "backward_tflops": round(fl / ms / 1e9, 3),
+            "pct_fp32_mfma_peak": round(100 * fl / ms / 1e9 / 157.3, 2),
+            "forward_ms": round(fms, 3),
+            "forward_tflops": round(rqrcp_flops(m, n, k, b, p) / fms / 1e9, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +295,8 @@ def main():
     ap.add_argument("--matrix", choices=("lowrank", "gaussian"), default="lowrank",
                     help="gaussian: i.i.d. N(0,1) A of the same size (no QR in the generator; "
                          "for profiler runs, where kernel times depend only on the sizes)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the measurements of the other forms")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain elementwise copy of this many MiB "
                          "(FP64), whose HBM counters calibrate the trailing update's")
@@ -198,6 +407,23 @@ def main():
             "algorithmic_gbps": round(tr_by / (tr_ms / 1e3) / 1e9, 1) if tr_ms > 0 else None,
         },
     }
+    if not args.no_extras:
+        extras = {}
+        f_last = rq.Factorization(copies[-1], jpvt, tau, bsk, info, K, B)
+        for name, fn in (("srqr", lambda: extra_srqr(rq, a0, f_last)),
+                         ("full_rank", lambda: extra_full_rank(rq)),
+                         ("mixed", lambda: extra_mixed(rq)),
+                         ("batched", lambda: extra_batched(rq)),
+                         ("backward", lambda: extra_backward(rq))):
+            if name != "srqr":
+                copies = None
+                f_last = None
+                torch.cuda.empty_cache()
+            log(f"extra measurement: {name} ...")
+            t0 = time.perf_counter()
+            extras[name] = fn()
+            log(f"  {name} done in {time.perf_counter() - t0:.1f} s: {extras[name]}")
+        line["extras"] = extras
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(a0, args.cpu_sample_k)

@@ -219,8 +219,9 @@ int rqrcp_batched_workspace_size(size_t *bytes);
  * prm: a_type = RQRCP_F32, sketch_type = RQRCP_F64, b, p, seed.  *_elems are the
  * pool sizes in elements; a problem whose descriptor does not fit the kernel's
  * limits or the pools is skipped with info[j] = -1.  info[j] otherwise as in
- * rqrcp_factor.  The kernel variant comes from the handle's tuning table
- * (rqrcp_autotune_batched), default variant 0. */
+ * rqrcp_factor.  The kernel variant comes from the library's tuning table
+ * (rqrcp_autotune_batched; one per device, shared by all handles of the
+ * process), default variant 0. */
 int rqrcp_factor_batched(rqrcp_handle h, int batch, const rqrcp_problem *probs,
                          const rqrcp_params *prm, float *A_pool, int64_t a_elems,
                          int32_t *jpvt_pool, int64_t jpvt_elems, double *tau_pool,
@@ -229,7 +230,7 @@ int rqrcp_factor_batched(rqrcp_handle h, int batch, const rqrcp_problem *probs,
 /* Autotuner: for every kernel variant, restores A_pool from A_orig (a device
  * copy of the inputs with the same layout, a_elems floats), runs the variant
  * twice and times the second run with HIP events; stores the fastest in the
- * handle's table for (b, b+p) and finally runs it once more, so the outputs
+ * library's table for (device, b, b+p) and finally runs it once more, so the outputs
  * hold its factorization.  Synchronizes.  best_variant and ms_per_variant
  * (host, may be NULL; at most 8 entries) report the measurements. */
 int rqrcp_autotune_batched(rqrcp_handle h, int batch, const rqrcp_problem *probs,

@@ -340,6 +340,34 @@ class SRQR:
     info: object    # int32 (1,): 0, or -max_swaps if the cap was reached
 
 
+def srqr_into(a0, fact, g, seed=0, *, d=16, exact=False, max_swaps=-1, ws=None):
+    """srqr_swap on an existing l-step factorization ``fact`` of ``a0`` (in place:
+    fact.a, fact.jpvt; returns (tau of length l+1, g2, nswaps, info) tensors)."""
+    torch = _torch()
+    m, n = a0.shape
+    l, b = fact.k, fact.block
+    p = fact.b.shape[0] - b
+    dev = a0.device
+    tau = torch.zeros(l + 1, dtype=torch.float64, device=dev)
+    tau[:l].copy_(fact.tau[:l])
+    g2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    ns = torch.zeros(1, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    flags = SRQR_EXACT if exact else 0
+    prm = Params(b, p, seed, F64, F64, 0)
+    lib = load_library()
+    nb = ctypes.c_size_t()
+    _check(lib.srqr_workspace_size(m, n, l, ctypes.byref(prm), d, flags, ctypes.byref(nb)),
+           "srqr_workspace_size")
+    if ws is None or ws.numel() < nb.value:
+        ws = workspace(nb.value, dev)
+    _check(lib.srqr_swap(handle(), m, n, l, ctypes.byref(prm), float(g), d, max_swaps, flags,
+                         _ptr(a0), _ld(a0), _ptr(fact.a), _ld(fact.a), _ptr(fact.jpvt),
+                         _ptr(tau), _ptr(fact.b), _ld(fact.b), _ptr(g2), _ptr(ns), _ptr(info),
+                         _ptr(ws), ws.numel()), "srqr_swap")
+    return tau, g2, ns, info
+
+
 def srqr(a0, l, b, p, g, seed=0, *, d=16, exact=False, max_swaps=-1, sketch_b=None):
     """Alg. 3: the l-step RQRCP of ``a0`` followed by spectrum-revealing swaps.
 

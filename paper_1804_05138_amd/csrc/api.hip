@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -36,8 +37,6 @@ struct rqrcp_ctx {
     double flops, bytes;
   };
   bool timing = false;
-  // batched kernel variant per (b, b + p), -1 = not tuned (autotuner table)
-  int batched_variant[17][33];
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
   double ms[RQRCP_NPHASES] = {};
@@ -362,8 +361,6 @@ int rqrcp_create(rqrcp_handle* h, void* stream) {
   if (!c) return RQRCP_ERR_HIP;
   c->stream = (hipStream_t)stream;
   c->device = dev;
-  for (auto& row : c->batched_variant)
-    for (int& v : row) v = -1;
   *h = c;
   return 0;
 }
@@ -662,6 +659,30 @@ int rqrcp_backward(rqrcp_handle h, int m, int n, int k, int b, int a_type, const
                           ldda, w);
 }
 
+// The autotuner's table: batched kernel variant per (device, b, b + p), shared
+// by every handle of the process (a graph captured on another stream's handle
+// uses the tuned variant too); -1 = not tuned.
+static std::mutex g_tune_mu;
+static int g_tune[64][17][33];
+static bool g_tune_init = false;
+
+static int tuned_variant(int dev, int b, int l) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune_init || dev < 0 || dev >= 64) return -1;
+  return g_tune[dev][b][l];
+}
+
+static void set_tuned_variant(int dev, int b, int l, int v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune_init) {
+    for (auto& d : g_tune)
+      for (auto& r : d)
+        for (int& x : r) x = -1;
+    g_tune_init = true;
+  }
+  if (dev >= 0 && dev < 64) g_tune[dev][b][l] = v;
+}
+
 int rqrcp_batched_limits(int* max_m, int* max_ln, int* max_b, int* max_l) {
   return batched_max(max_m, max_ln, max_b, max_l);
 }
@@ -702,7 +723,7 @@ int rqrcp_factor_batched(rqrcp_handle h, int batch, const rqrcp_problem* probs,
   if (rc) return rc;
   if (batch == 0) return 0;
   const int l = prm->b + prm->p;
-  int v = h->batched_variant[prm->b][l];
+  int v = tuned_variant(h->device, prm->b, l);
   if (v < 0) v = 0;
   return launch_batched(h->stream, v, batch, probs, prm->b, l, prm->seed, A_pool, a_elems,
                         jpvt_pool, jpvt_elems, tau_pool, tau_elems, B_pool, b_elems, info,
@@ -748,7 +769,7 @@ int rqrcp_autotune_batched(rqrcp_handle h, int batch, const rqrcp_problem* probs
   }
   h->pool.push_back(e0);
   h->pool.push_back(e1);
-  h->batched_variant[prm->b][l] = best;
+  set_tuned_variant(h->device, prm->b, l, best);
   if (best_variant) *best_variant = best;
   // leave the outputs of the chosen variant
   RQ_HIP_CHECK(hipMemcpyAsync(A_pool, A_orig, (size_t)a_elems * sizeof(float),

@@ -35,3 +35,21 @@ def rqrcp_flops(m: int, n: int, k: int, b: int, p: int) -> float:
 
 def qr_equivalent_flops(m: int, n: int, k: int) -> float:
     return 4.0 * m * n * k - 2.0 * (m + n) * k * k + 4.0 * k ** 3 / 3.0
+
+
+def backward_flops(m: int, n: int, k: int, b: int) -> float:
+    """Algorithmic flops of the frozen-pivot adjoint as the library computes it:
+    Q1 from the reflectors (per block: V^T Q, T Y, Q -= V Z and the Gram V^T V),
+    R11^-1, and the products A2 R12_bar^T, Q1 R12_bar, R11 R11_bar^T,
+    Q1_bar'^T Q1, Q1 copyltu(M) and (.) R11^-T."""
+    total = 0.0
+    j = 0
+    while j < k:
+        bb = min(b, k - j)
+        rows, nc = m - j, k - j
+        total += 2.0 * rows * bb * bb + 4.0 * rows * bb * nc + 2.0 * bb * bb * nc
+        j += bb
+    n2 = n - k
+    total += k ** 3 / 3.0
+    total += 4.0 * m * k * n2 + 2.0 * k ** 3 + 6.0 * m * k * k
+    return total

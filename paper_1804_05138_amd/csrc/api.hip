@@ -165,6 +165,8 @@ __global__ void k_init(QrcpScratch* q, PanelScratch* p, int* info, int* jpvt, in
                        double* cand, long long ncand) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   for (long long e = t; e < ncand; e += (long long)gridDim.x * blockDim.x) cand[e] = 0.0;
+  for (int e = t; e < (int)(sizeof(p->sub) / sizeof(unsigned)); e += gridDim.x * blockDim.x)
+    p->sub[e] = 0u;
   if (t == 0) {
     q->bar.count = 0;
     q->bar.err = 0;

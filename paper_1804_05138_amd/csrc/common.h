@@ -143,7 +143,36 @@ RQ_DEV bool grid_arrive(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {
     bl->last = (arrived == nwg - 1) ? 1u : 0u;
   }
   __syncthreads();
-  return bl->last != 0;
+  return __builtin_amdgcn_readfirstlane(bl->last) != 0;  // uniform for the compiler too
+}
+
+// Two-level arrive: workgroups count themselves in groups of GRID_GROUP on
+// separate counters (sub[grp * GRID_SUB_STRIDE]); the last of each group
+// counts the group on bar->count.  Fewer atomics queue on any one address
+// than with a single counter.  Same contract as grid_arrive: returns true in
+// every thread of the workgroup that completed the barrier, which then sees
+// every workgroup's writes made before its arrival (acquire-release chain).
+constexpr int GRID_GROUP = 16;
+constexpr int GRID_SUB_STRIDE = 32;  // one 128-byte line per group counter
+RQ_DEV bool grid_arrive2(GridBarrier* bar, unsigned* sub, unsigned nwg, BarrierLocal* bl) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned grp = blockIdx.x / GRID_GROUP;
+    const unsigned ngrp = (nwg + GRID_GROUP - 1) / GRID_GROUP;
+    const unsigned gsize = min((unsigned)GRID_GROUP, nwg - grp * GRID_GROUP);
+    unsigned* c = sub + grp * GRID_SUB_STRIDE;
+    const unsigned a = __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned last = 0u;
+    if (a == gsize - 1) {
+      __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned b =
+          __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      last = (b == ngrp - 1) ? 1u : 0u;
+    }
+    bl->last = last;
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(bl->last) != 0;  // uniform for the compiler too
 }
 
 // Phase 2a (all threads of the last workgroup): release the others.

@@ -17,9 +17,10 @@ struct QrcpScratch {
   int pad[63];
 };
 
-// Scratch of the persistent panel kernel.
+// Scratch of the persistent panel kernel: the barrier and its group counters.
 struct PanelScratch {
   GridBarrier bar;
+  unsigned sub[64 * 32];  // up to 1024 workgroups, one line per group of 16
 };
 
 constexpr int MAX_B = 128;      // largest block size b the kernels accept

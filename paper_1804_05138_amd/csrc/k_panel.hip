@@ -204,6 +204,251 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, T* __restrict__ a, long 
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Register-resident form of the same algorithm (the default).  Thread
+// (cc, grp) = (tid % BBM, tid / BBM) holds column cc of the panel for the rows
+// rs + grp + NG j, j < RPT, of its workgroup's slab in registers (FP64), so a
+// reflector step is: broadcast column t through LDS, RPT fused multiply-adds
+// of partial dot products, a reduction over the NG row groups, the grid-wide
+// sum, and RPT multiply-adds of update -- all unrolled.  Columns past bb are
+// zero padding up to the compile-time width BBM.
+// ---------------------------------------------------------------------------
+constexpr int RPT = 32;  // panel rows per thread
+
+template <typename T, int BBM>
+__global__ __launch_bounds__(PT, 2) void k_panel_r(int m, T* __restrict__ a, long long lda, int i,
+                                                    int bb, int bbp,
+                                                    const double* __restrict__ wp, long long ldw,
+                                                    double* __restrict__ tau,
+                                                    double* __restrict__ tmat, GridBarrier* bar,
+                                                    unsigned* __restrict__ bsub,
+                                                    double* __restrict__ gpart) {
+  constexpr int NG = PT / BBM;       // row groups
+  constexpr int R = NG * RPT;        // slab rows per workgroup
+  constexpr int QC = 4096 / R;       // reflector columns per staging chunk (32 KB)
+  __shared__ double s_col[R];        // column t of the step, by local row
+  __shared__ double s_v[QC * R];     // previous block's reflectors, [q][local row]
+  __shared__ double s_red[NG * BBM];
+  __shared__ double s_row[2][BBM];   // pivot row, by step parity
+  __shared__ double s_S[2][BBM];     // grid-wide dot products, by step parity
+  __shared__ double s_t[MAX_B * MAX_B / 4];  // T of widths <= 64 (wider: in global)
+  __shared__ unsigned s_flag;
+  __shared__ BarrierLocal bl;
+
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int cc = tid % BBM, grp = tid / BBM;
+  const int rp = i - bbp;
+  const int rs = rp + g * R;
+  const int ngrp = (G + GRID_GROUP - 1) / GRID_GROUP;  // barrier groups of workgroups
+  const int mygrp = g / GRID_GROUP;
+  const int gfirst = mygrp * GRID_GROUP, gsize = min(GRID_GROUP, G - gfirst);
+  double* growbuf = gpart + 2 * (size_t)G * BBM;  // [2][BBM] pivot rows
+  double* gsum = growbuf + 2 * BBM;               // [2][BBM] grid-wide sums
+  double* ggrp = gsum + 2 * BBM;                  // [2][64][BBM] group sums
+  double* gz = ggrp + 2 * 64 * BBM;               // [bb][bb] columns V^T v_t for T
+  grid_sync_init(bar, &bl);
+
+  // ---- load my rows of column cc (zero outside the panel and past m) ----
+  double x[RPT];
+  {
+    const T* col = a + (long long)(i + (cc < bb ? cc : 0)) * lda;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int r = rs + grp + NG * j;
+      const T v = col[r < m ? r : m - 1];
+      x[j] = (cc < bb && r < m) ? (double)v : 0.0;
+    }
+  }
+
+  // ---- pending update of the previous block: x -= V_prev(rows, :) W'(:, cc) ----
+  for (int q0 = 0; q0 < bbp; q0 += QC) {
+    __syncthreads();
+    for (int e = tid; e < QC * R; e += PT) {
+      const int q = q0 + e / R, lr = e % R;
+      const int r = rs + lr;
+      const int d = r - rp;
+      double v = 0.0;
+      if (q < bbp && r < m)
+        v = (d > q) ? (double)a[(long long)(rp + q) * lda + r] : (d == q ? 1.0 : 0.0);
+      s_v[(e / R) * R + lr] = v;
+    }
+    __syncthreads();
+    const double* wcol = wp + (long long)(cc < bb ? cc : 0) * ldw;
+    for (int qq = 0; qq < QC && q0 + qq < bbp; ++qq) {
+      const double w = (cc < bb) ? wcol[q0 + qq] : 0.0;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) x[j] -= s_v[qq * R + grp + NG * j] * w;
+    }
+  }
+
+  for (int t = 0; t < bb; ++t) {
+    const int gr = i + t;
+    const int lgr = gr - rs;  // local index of the pivot row (may be outside the slab)
+    const int par = t & 1;
+    double* gp = gpart + (size_t)par * G * BBM;
+    double* gg = ggrp + (size_t)par * 64 * BBM;
+    // ---- broadcast column t and the pivot row ----
+    if (cc == t) {
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) s_col[grp + NG * j] = x[j];
+    }
+    if (lgr >= 0 && lgr < R && grp == lgr % NG) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) v = (grp + NG * j == lgr) ? x[j] : v;
+      growbuf[par * BBM + cc] = v;
+    }
+    __syncthreads();
+    double xt[RPT];
+    double d = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      xt[j] = s_col[grp + NG * j];
+      d += (grp + NG * j > lgr) ? xt[j] * x[j] : 0.0;
+    }
+    s_red[grp * BBM + cc] = d;
+    __syncthreads();
+    if (grp == 0) {
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) sum += s_red[q * BBM + cc];
+      gp[(size_t)g * BBM + cc] = sum;
+    }
+    // ---- two-level reduction over the grid (fixed order, so the result does
+    // not depend on which workgroups finish last):
+    //   the last workgroup of each group of GRID_GROUP adds its group's rows,
+    //   the last group adds the group sums, publishes them and releases ----
+    __syncthreads();
+    if (tid == 0) {
+      unsigned* c = bsub + mygrp * GRID_SUB_STRIDE;
+      const unsigned a0 = __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      s_flag = (a0 == (unsigned)gsize - 1) ? 1u : 0u;
+      if (s_flag) __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    bool released = false;
+    if (__builtin_amdgcn_readfirstlane(s_flag)) {
+      // group rows gfirst .. gfirst + gsize - 1 (at most GRID_GROUP / NG per thread)
+      double sum = 0.0;
+      {
+        double v[GRID_GROUP / NG > 0 ? GRID_GROUP / NG : 1];
+#pragma unroll
+        for (int u = 0; u < (GRID_GROUP / NG > 0 ? GRID_GROUP / NG : 1); ++u) {
+          const int q = grp + NG * u;
+          v[u] = (q < gsize) ? gp[(size_t)(gfirst + q) * BBM + cc] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < (GRID_GROUP / NG > 0 ? GRID_GROUP / NG : 1); ++u) sum += v[u];
+      }
+      s_red[grp * BBM + cc] = sum;
+      __syncthreads();
+      if (grp == 0) {
+        double tot = 0.0;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) tot += s_red[q * BBM + cc];
+        gg[(size_t)mygrp * BBM + cc] = tot;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const unsigned b0 =
+            __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_flag = (b0 == (unsigned)ngrp - 1) ? 1u : 0u;
+      }
+      __syncthreads();
+      if (__builtin_amdgcn_readfirstlane(s_flag)) {
+        // the group sums, in group order (at most 64 / NG per thread)
+        double sum2 = 0.0;
+        {
+          constexpr int U = (64 + NG - 1) / NG;
+          double v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = grp + NG * u;
+            v[u] = (q < ngrp) ? gg[(size_t)q * BBM + cc] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) sum2 += v[u];
+        }
+        s_red[grp * BBM + cc] = sum2;
+        __syncthreads();
+        if (grp == 0) {
+          double tot = 0.0;
+#pragma unroll
+          for (int q = 0; q < NG; ++q) tot += s_red[q * BBM + cc];
+          s_S[par][cc] = tot;
+          gsum[par * BBM + cc] = tot;
+        }
+        grid_release(bar, &bl);
+        released = true;
+      }
+    }
+    if (!released) {
+      grid_wait(bar, &bl);
+      if (grp == 0) s_S[par][cc] = gsum[par * BBM + cc];
+    }
+    if (grp == 0) s_row[par][cc] = growbuf[par * BBM + cc];
+    __syncthreads();
+    // ---- the reflector (dlarfg) and its update, computed by every thread ----
+    const double alpha = s_row[par][t], xn2 = s_S[par][t];
+    double beta = alpha, tt = 0.0, den = 1.0;
+    if (xn2 > 0.0) {
+      const double nrm = hypot(alpha, sqrt(xn2));
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      tt = (beta - alpha) / beta;
+      den = alpha - beta;
+    }
+    if (g == 0 && tid == 0) tau[i + t] = tt;
+    const double vta = s_row[par][cc] + s_S[par][cc] / den;  // v_t^T a_cc
+    if (g == 0 && grp == 0 && cc < bb) gz[t * bb + cc] = (cc < t) ? vta : 0.0;
+    // f = tau (v^T a_cc) for cc > t; g = f / (alpha - beta)
+    const double fc = (cc > t && cc < bb && tt != 0.0) ? tt * vta : 0.0;
+    const double gc = fc / den;
+    // column t itself: rows below the pivot become v = x / (alpha - beta)
+    const bool ist = cc == t;
+    const double sc = (ist && tt != 0.0) ? 1.0 / den : 1.0;
+    // selects only: no branches in the unrolled loop
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int lr = grp + NG * j;
+      const double v = x[j];
+      const double below = ist ? xt[j] * sc : v - xt[j] * gc;
+      const double piv = ist ? beta : v - fc;
+      x[j] = (lr > lgr) ? below : ((lr == lgr) ? piv : v);
+    }
+  }
+
+  // ---- write my rows back ----
+  if (cc < bb) {
+    T* col = a + (long long)(i + cc) * lda;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int r = rs + grp + NG * j;
+      if (r < m) col[r] = (T)x[j];
+    }
+  }
+
+  // ---- T from the stored (V^T v_t) columns; workgroup 0 wrote every tau and gz ----
+  if (g == 0) {
+    __syncthreads();
+    double* Tm = (bb * bb <= MAX_B * MAX_B / 4) ? s_t : tmat;
+    for (int e = tid; e < bb * bb; e += PT) Tm[e] = 0.0;
+    __syncthreads();
+    for (int t = 0; t < bb; ++t) {
+      const double tt = tau[i + t];
+      if (tid < t) {
+        double acc = 0.0;
+        for (int c = tid; c < t; ++c) acc += Tm[c * bb + tid] * gz[t * bb + c];
+        Tm[t * bb + tid] = -tt * acc;
+      }
+      if (tid == t) Tm[t * bb + t] = tt;
+      __syncthreads();
+    }
+    if (Tm == s_t)
+      for (int e = tid; e < bb * bb; e += PT) tmat[e] = Tm[e];
+  }
+}
+
 }  // namespace
 
 static int panel_rows_per_wg(int bb, int bbp) {
@@ -214,10 +459,18 @@ static int panel_rows_per_wg(int bb, int bbp) {
   return R < 16 ? 16 : R;
 }
 
+static int panel_bbm(int bb) { return bb <= 16 ? 16 : bb <= 32 ? 32 : bb <= 64 ? 64 : 128; }
+
 size_t panel_partial_doubles(int rows, int bb) {
   const int R = panel_rows_per_wg(bb, MAX_B);
   const size_t G = (size_t)(rows + R - 1) / R;
-  return 2 * G * bb + 2 * (size_t)bb + (size_t)bb * bb + 64;
+  const int bbm = panel_bbm(bb);
+  const size_t Rr = (size_t)(PT / bbm) * RPT;
+  const size_t Gr = (rows + Rr - 1) / Rr;
+  const size_t old_need = 2 * G * bb + 2 * (size_t)bb + (size_t)bb * bb + 64;
+  const size_t reg_need = 2 * Gr * bbm + 4 * (size_t)bbm + 2 * 64 * (size_t)bbm +
+                          (size_t)bb * bb + 64;
+  return old_need > reg_need ? old_need : reg_need;
 }
 
 int panel_grid(int rows, int bb) {
@@ -225,11 +478,47 @@ int panel_grid(int rows, int bb) {
   return (rows + R - 1) / R;
 }
 
+template <typename T, int BBM>
+static int launch_panel_r(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
+                          const double* wp, long long ldw, double* tau, double* t,
+                          PanelScratch* scr, double* partial, bool* launched) {
+  *launched = false;
+  const int rows = m - (i - bbp);
+  constexpr int R = (PT / BBM) * RPT;
+  const int G = (rows + R - 1) / R;
+  auto kern = &k_panel_r<T, BBM>;
+  int dev = 0, ncu = 0, per_cu = 0;
+  RQ_HIP_CHECK(hipGetDevice(&dev));
+  RQ_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  RQ_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(kern), PT, 0));
+  // the grid barrier needs every workgroup resident at once
+  if (G > ncu * per_cu) return RQ_OK;
+  if (G > 64 * GRID_GROUP) return RQ_OK;
+  hipLaunchKernelGGL(kern, dim3(G), dim3(PT), 0, s, m, a, lda, i, bb, bbp, wp, ldw, tau, t,
+                     &scr->bar, scr->sub, partial);
+  RQ_HIP_CHECK(hipGetLastError());
+  *launched = true;
+  return RQ_OK;
+}
+
 template <typename T>
 int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
                  const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
                  double* partial) {
   if (bb < 1 || bb > MAX_B || bbp < 0 || bbp > MAX_B) return RQ_ERR_LIMIT;
+  {
+    bool done = false;
+    int rc = RQ_OK;
+    switch (panel_bbm(bb)) {
+      case 16: rc = launch_panel_r<T, 16>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done); break;
+      case 32: rc = launch_panel_r<T, 32>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done); break;
+      case 64: rc = launch_panel_r<T, 64>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done); break;
+      default: rc = launch_panel_r<T, 128>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done); break;
+    }
+    if (rc || done) return rc;
+  }
+  // too many rows for one resident grid of the register form: LDS-slab form
   const int rows = m - (i - bbp);
   const int R = panel_rows_per_wg(bb, MAX_B);
   const int G = (rows + R - 1) / R;

@@ -230,9 +230,10 @@ RQ_DEV void wait_all_seq(const unsigned* seq0, long long stride, int n, unsigned
         if ((spins & 1023u) == 0 && atomic_peek_agent(&bar->err)) break;
       }
     }
+    // one acquire for the workgroup (the invalidation is per cache, not per wave)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 RQ_DEV void grid_barrier(GridBarrier* bar, unsigned nwg, BarrierLocal* bl) {

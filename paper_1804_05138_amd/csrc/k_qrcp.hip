@@ -231,26 +231,21 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
     }
 
     // ---- (4) apply H = I - tau v v^T to the active columns, new norms ----
-    if (active) {
-      if (tau != 0.0) {
-        double d = 0.0;
+    // (branch-free: finished columns take f = 0 and their norms are unused)
+    {
+      double d = 0.0;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const int r = j * TPC + sub;
-          d += s_v[r < l ? r : MAX_L - 1] * x[j];  // rows past l hold x = 0
-        }
-        d = tpc_sum<TPC>(d);
-        const double f = tau * d;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const int r = j * TPC + sub;
-          x[j] -= f * s_v[r < l ? r : MAX_L - 1];
-        }
+      for (int j = 0; j < RPT; ++j) {
+        const int r = j * TPC + sub;
+        d += s_v[r < l ? r : MAX_L - 1] * x[j];  // rows past l hold x = 0
       }
+      d = tpc_sum<TPC>(d);
+      const double f = active ? tau * d : 0.0;
       double nn = 0.0;
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const int r = j * TPC + sub;
+        x[j] -= f * s_v[r < l ? r : MAX_L - 1];
         nn += (r > t) ? x[j] * x[j] : 0.0;
       }
       nrm2 = tpc_sum<TPC>(nn);

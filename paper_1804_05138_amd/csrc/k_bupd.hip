@@ -77,6 +77,103 @@ __global__ __launch_bounds__(BT) void k_bupdate(int m, const T* __restrict__ a, 
   }
 }
 
+
+// Staged form for block widths up to 64 (the default): every global access is
+// coalesced (column-major tiles move through LDS with a padded row pitch), and
+// T, the diagonal block of A (R11 above, V11 below) and Rhat11 are read from
+// LDS, so the triangular solve's dependent chain never waits on memory.
+constexpr int SB = 64;        // largest block width of the staged form
+constexpr int CW = 64;        // columns per workgroup
+constexpr int SP = CW + 1;    // LDS row pitch of the column tiles
+constexpr int AP = SB + 1;    // LDS pitch of the bb x bb blocks
+
+template <typename T>
+__global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* __restrict__ a, long long lda,
+                                                  int i, int bb, const double* __restrict__ tm,
+                                                  const T* __restrict__ wpart, int nsplit,
+                                                  double* __restrict__ wp, long long ldw,
+                                                  double* __restrict__ bsk, long long ldb,
+                                                  int c0, int ncols, const int* __restrict__ info) {
+  extern __shared__ double smem[];
+  double* sT = smem;                 // T(q, r) at sT[r * AP + q]; later Rhat11(q, r)
+  double* sA = sT + SB * AP;         // A(i + r, i + c) at sA[c * AP + r]
+  double* sW = sA + SB * AP;         // [q][col]: W, then R12, then the B delta
+  double* sX = sW + SB * SP;         // [q][col]: W', then X
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, part = tid >> 6;
+  const int cb = blockIdx.x * CW;                 // first column (relative to c0)
+  const int nc = min(CW, ncols - cb);             // columns of this workgroup
+  const int col = c0 + cb + lane;
+  const bool ok = lane < nc;
+
+  for (int e = tid; e < bb * bb; e += BT) {
+    const int r = e / bb, q = e % bb;
+    sT[r * AP + q] = tm[r * bb + q];
+    sA[r * AP + q] = (double)a[(long long)(i + r) * lda + i + q];  // column r, row q
+  }
+  // W(:, cb + c) = sum of the split partials (contiguous per column)
+  for (int e = tid; e < nc * bb; e += BT) {
+    const int c = e / bb, q = e % bb;
+    double s = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp)
+      s += (double)wpart[((long long)sp * ncols + cb + c) * bb + q];
+    sW[q * SP + c] = s;
+  }
+  __syncthreads();
+  // W' = T^T W
+  for (int r = part; r < bb; r += 4) {
+    double s = 0.0;
+    for (int q = 0; q <= r; ++q) s += sT[r * AP + q] * sW[q * SP + lane];
+    sX[r * SP + lane] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < nc * bb; e += BT) {
+    const int c = e / bb, r = e % bb;
+    wp[(long long)(cb + c) * ldw + r] = sX[r * SP + c];
+  }
+  if (bsk == nullptr || *info != 0) return;
+  // Rhat11 = triu(B(0:bb, i:i+bb)) into sT; R12 starts as A(i:i+bb, col)
+  for (int e = tid; e < bb * bb; e += BT) {
+    const int r = e / bb, q = e % bb;   // column r, row q
+    sT[r * AP + q] = (q <= r) ? bsk[(long long)(i + r) * ldb + q] : 0.0;
+  }
+  for (int e = tid; e < nc * bb; e += BT) {
+    const int c = e / bb, r = e % bb;
+    sW[r * SP + c] = (double)a[(long long)(c0 + cb + c) * lda + i + r];
+  }
+  __syncthreads();
+  // R12 = A(i:i+bb, col) - V11 W'   (V11 unit lower: A(i + r, i + q), q < r)
+  for (int r = part; r < bb; r += 4) {
+    double s = sW[r * SP + lane] - sX[r * SP + lane];
+    for (int q = 0; q < r; ++q) s -= sA[q * AP + r] * sX[q * SP + lane];
+    sW[r * SP + lane] = s;
+  }
+  __syncthreads();
+  // X = R11^{-1} R12 (back substitution, one column per lane of wave 0)
+  if (part == 0) {
+    for (int r = bb - 1; r >= 0; --r) {
+      double s = sW[r * SP + lane];
+      for (int q = r + 1; q < bb; ++q) s -= sA[q * AP + r] * sX[q * SP + lane];
+      sX[r * SP + lane] = s / sA[r * AP + r];
+    }
+  }
+  __syncthreads();
+  // delta = Rhat11 X, then B(0:bb, col) -= delta
+  for (int r = part; r < bb; r += 4) {
+    double s = 0.0;
+    for (int q = r; q < bb; ++q) s += sT[q * AP + r] * sX[q * SP + lane];
+    sW[r * SP + lane] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < nc * bb; e += BT) {
+    const int c = e / bb, r = e % bb;
+    bsk[(long long)(c0 + cb + c) * ldb + r] -= sW[r * SP + c];
+  }
+  (void)ok;
+  (void)col;
+  (void)m;
+}
+
 }  // namespace
 
 template <typename T>
@@ -85,6 +182,15 @@ int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int b
                    double* bsk, long long ldb, int c0, int ncols, const int* info) {
   if (ncols <= 0) return RQ_OK;
   if (bb > MAX_B) return RQ_ERR_LIMIT;
+  if (bb <= SB) {
+    const size_t shmem = (2 * (size_t)SB * AP + 2 * (size_t)SB * SP) * sizeof(double);
+    RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bupdate_s<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    hipLaunchKernelGGL(k_bupdate_s<T>, dim3((ncols + CW - 1) / CW), dim3(BT), shmem, s, m, a, lda,
+                       i, bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info);
+    RQ_HIP_CHECK(hipGetLastError());
+    return RQ_OK;
+  }
   hipLaunchKernelGGL(k_bupdate<T>, dim3((ncols + 63) / 64), dim3(BT), 0, s, m, a, lda, i, bb, t,
                      wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info);
   RQ_HIP_CHECK(hipGetLastError());

@@ -21,6 +21,7 @@ struct QrcpScratch {
 struct PanelScratch {
   GridBarrier bar;
   unsigned sub[64 * 32];  // up to 1024 workgroups, one line per group of 16
+  int cq_flag[64];        // 1: the Cholesky-QR panel path produced the panel
 };
 
 constexpr int MAX_B = 128;      // largest block size b the kernels accept
@@ -70,6 +71,14 @@ int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int b
                  const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
                  double* partial);
 size_t panel_partial_doubles(int rows, int bb);
+// Cholesky-QR2 panel path (k_panel_cq.hip), used by launch_panel for bb <= 64
+// and panels at least twice as tall as wide.
+bool panel_cq_applicable(int m, int i, int bb);
+size_t panel_cq_doubles(int rows);
+template <typename T>
+int launch_panel_cq(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
+                    const double* wp, long long ldw, double* tau, double* tmat, double* scratch,
+                    int* flag);
 
 // Trailing pass over columns [c_begin, c_end) of A, rows [i, m):
 //   if bbu > 0:  A(i:m, c) -= V_i * Wp(:, c - w0)      (V_i = A(i:m, i:i+bbu) reflectors)

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(PT, 1) void k_panel(int m, T* __restrict__ a, long 
                                                  const double* __restrict__ wp, long long ldw,
                                                  double* __restrict__ tau, double* __restrict__ tmat,
                                                  GridBarrier* bar, double* __restrict__ gpart,
-                                                 int R) {
+                                                 int R, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // the panel was already factored by another path
   extern __shared__ double lds[];
   const int ldp = bb + 1;
   double* P = lds;                      // R x bb panel slab, row stride ldp
@@ -223,7 +224,9 @@ __global__ __launch_bounds__(PT, 2) void k_panel_r(int m, T* __restrict__ a, lon
                                                     double* __restrict__ tau,
                                                     double* __restrict__ tmat, GridBarrier* bar,
                                                     unsigned* __restrict__ bsub,
-                                                    double* __restrict__ gpart) {
+                                                    double* __restrict__ gpart,
+                                                    const int* __restrict__ skip) {
+  if (skip && *skip) return;  // the panel was already factored by another path
   constexpr int NG = PT / BBM;       // row groups
   constexpr int R = NG * RPT;        // slab rows per workgroup
   constexpr int QC = 4096 / R;       // reflector columns per staging chunk (32 KB)
@@ -461,7 +464,7 @@ static int panel_rows_per_wg(int bb, int bbp) {
 
 static int panel_bbm(int bb) { return bb <= 16 ? 16 : bb <= 32 ? 32 : bb <= 64 ? 64 : 128; }
 
-size_t panel_partial_doubles(int rows, int bb) {
+static size_t stepwise_partial_doubles(int rows, int bb) {
   const int R = panel_rows_per_wg(bb, MAX_B);
   const size_t G = (size_t)(rows + R - 1) / R;
   const int bbm = panel_bbm(bb);
@@ -473,6 +476,10 @@ size_t panel_partial_doubles(int rows, int bb) {
   return old_need > reg_need ? old_need : reg_need;
 }
 
+size_t panel_partial_doubles(int rows, int bb) {
+  return stepwise_partial_doubles(rows, bb) + panel_cq_doubles(rows);
+}
+
 int panel_grid(int rows, int bb) {
   const int R = panel_rows_per_wg(bb, MAX_B);
   return (rows + R - 1) / R;
@@ -481,7 +488,8 @@ int panel_grid(int rows, int bb) {
 template <typename T, int BBM>
 static int launch_panel_r(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
                           const double* wp, long long ldw, double* tau, double* t,
-                          PanelScratch* scr, double* partial, bool* launched) {
+                          PanelScratch* scr, double* partial, bool* launched,
+                          const int* skip) {
   *launched = false;
   const int rows = m - (i - bbp);
   constexpr int R = (PT / BBM) * RPT;
@@ -496,25 +504,24 @@ static int launch_panel_r(hipStream_t s, int m, T* a, long long lda, int i, int 
   if (G > ncu * per_cu) return RQ_OK;
   if (G > 64 * GRID_GROUP) return RQ_OK;
   hipLaunchKernelGGL(kern, dim3(G), dim3(PT), 0, s, m, a, lda, i, bb, bbp, wp, ldw, tau, t,
-                     &scr->bar, scr->sub, partial);
+                     &scr->bar, scr->sub, partial, skip);
   RQ_HIP_CHECK(hipGetLastError());
   *launched = true;
   return RQ_OK;
 }
 
 template <typename T>
-int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
-                 const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
-                 double* partial) {
-  if (bb < 1 || bb > MAX_B || bbp < 0 || bbp > MAX_B) return RQ_ERR_LIMIT;
+static int launch_stepwise(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
+                           const double* wp, long long ldw, double* tau, double* t,
+                           PanelScratch* scr, double* partial, const int* skip) {
   {
     bool done = false;
     int rc = RQ_OK;
     switch (panel_bbm(bb)) {
-      case 16: rc = launch_panel_r<T, 16>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done); break;
-      case 32: rc = launch_panel_r<T, 32>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done); break;
-      case 64: rc = launch_panel_r<T, 64>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done); break;
-      default: rc = launch_panel_r<T, 128>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done); break;
+      case 16: rc = launch_panel_r<T, 16>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done, skip); break;
+      case 32: rc = launch_panel_r<T, 32>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done, skip); break;
+      case 64: rc = launch_panel_r<T, 64>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done, skip); break;
+      default: rc = launch_panel_r<T, 128>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, &done, skip); break;
     }
     if (rc || done) return rc;
   }
@@ -534,9 +541,25 @@ int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int b
   // the grid barrier needs every workgroup resident at once
   if (G > ncu * per_cu) return RQ_ERR_LIMIT;
   hipLaunchKernelGGL(k_panel<T>, dim3(G), dim3(PT), shmem, s, m, a, lda, i, bb, bbp, wp, ldw, tau, t,
-                     &scr->bar, partial, R);
+                     &scr->bar, partial, R, skip);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
+}
+
+template <typename T>
+int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
+                 const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
+                 double* partial) {
+  if (bb < 1 || bb > MAX_B || bbp < 0 || bbp > MAX_B) return RQ_ERR_LIMIT;
+  if (panel_cq_applicable(m, i, bb)) {
+    // Cholesky-QR2 panel; the stepwise kernel runs only if that path declined
+    double* cqs = partial + stepwise_partial_doubles(m - (i - bbp), bb);
+    int rc = launch_panel_cq<T>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, cqs, scr->cq_flag);
+    if (rc) return rc;
+    return launch_stepwise<T>(s, m, a, lda, i, bb, 0, nullptr, 0, tau, t, scr, partial,
+                              scr->cq_flag);
+  }
+  return launch_stepwise<T>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, nullptr);
 }
 template int launch_panel<double>(hipStream_t, int, double*, long long, int, int, int,
                                   const double*, long long, double*, double*, PanelScratch*,

@@ -20,7 +20,8 @@
 // second Gram, the small-matrix step (Cholesky, modified LU, T, R), and the
 // write-back of V and R.  A flag in the scratch records whether the
 // factorization can be trusted (every Cholesky pivot positive and finite,
-// diag(R1) within a factor 1e6); if not, every later kernel of this path
+// diag(R1) within a factor 1e6, the pivots of the second Gram matrix within
+// [1/4, 4]); if not, every later kernel of this path
 // returns at once and the stepwise kernel, which reads the same flag, factors
 // the (already updated) panel instead.
 #include "internal.h"
@@ -524,7 +525,8 @@ __global__ __launch_bounds__(ST) void k_cq_small(int bb, const double* __restric
     const double sr = (r < bb) ? s_s[r] : 0.0;
     rh[c * CB + r] = (r <= c && c < bb) ? sr * rh0[e] : 0.0;
   }
-  if (tid == 0 && !ok) *flag = 0;
+  // the first pass left Q1 close to orthonormal: every pivot of G2 = Q1^T Q1 near 1
+  if (tid == 0 && !(ok && dmin > 0.25 && dmax < 4.0)) *flag = 0;
 }
 
 // ---- write V (rows below the top block: Q1 M2) and the top block (Rh / L1) ----

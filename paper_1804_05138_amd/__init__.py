@@ -61,6 +61,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"librqrcp.so not built ({path}); run paper_1804_05138_amd/build.py")
+    # torch first: the library must bind to the HIP runtime torch loads (its
+    # streams and allocations are passed straight through), not pull in a
+    # second copy that torch would then pick up in place of its own
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
     i64 = ctypes.c_int64

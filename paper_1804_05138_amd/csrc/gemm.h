@@ -6,14 +6,19 @@
 
 namespace rq {
 
+// ws (ws_elems elements, may be null): room for split-K partials; used when
+// the output has few tiles and K is long.
 template <typename T>
 int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, T alpha, const T* A, long long lda,
-         const T* B, long long ldb, T beta, T* C, long long ldc);
+         const T* B, long long ldb, T beta, T* C, long long ldc, T* ws = nullptr,
+         size_t ws_elems = 0);
+
+size_t splitk_elems(int m, int n);
 
 // Dense V (rows x bb), Gram V^T V and T of one reflector block.
 template <typename T>
 int block_t(hipStream_t s, int rows, int bb, const T* a, long long lda, const double* tau, T* vd,
-            T* gram, T* tm);
+            T* gram, T* tm, T* ws = nullptr, size_t ws_elems = 0);
 
 size_t form_q_work_elems(int m, int k, int b);
 
@@ -23,7 +28,7 @@ int form_q(hipStream_t s, int m, int k, int b, const T* a, long long lda, const 
 
 // Frozen-pivot adjoint (k_backward.hip): byte offsets of its workspace.
 struct BackwardLayout {
-  size_t q1, a2, qb, g, r11, rinv, mm, formq, total;
+  size_t q1, a2, qb, g, r11, rinv, mm, formq, sk, total;
 };
 BackwardLayout backward_layout(int m, int n, int k, int b, size_t es);
 template <typename T>

@@ -164,6 +164,7 @@ BackwardLayout backward_layout(int m, int n, int k, int b, size_t es) {
   L.rinv = take((size_t)k * k);
   L.mm = take((size_t)k * k);
   L.formq = take(form_q_work_elems(m, k, b));
+  L.sk = take(splitk_elems(k, k));
   L.total = off;
   return L;
 }
@@ -182,6 +183,8 @@ int backward(hipStream_t s, int m, int n, int k, int b, const T* a, long long ld
   T* rinv = (T*)(ws + L.rinv);
   T* mm = (T*)(ws + L.mm);
   T* fq = (T*)(ws + L.formq);
+  T* sk = (T*)(ws + L.sk);
+  const size_t skn = splitk_elems(k, k);
   const int n2 = n - k;
   int rc;
   // Q1 from (V, tau), A2 = (A Pi)(:, k:n), R11
@@ -219,7 +222,7 @@ int backward(hipStream_t s, int m, int n, int k, int b, const T* a, long long ld
     rc = RQ_OK;
   }
   if (rc) return rc;
-  rc = gemm<T>(s, true, false, k, k, m, T(-1), qb, m, q1, m, T(1), mm, k);
+  rc = gemm<T>(s, true, false, k, k, m, T(-1), qb, m, q1, m, T(1), mm, k, sk, skn);
   if (rc) return rc;
   hipLaunchKernelGGL(k_copyltu<T>, dim3(grid_for((long long)k * k)), dim3(BT), 0, s, k, mm,
                      (long long)k);

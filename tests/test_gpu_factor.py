@@ -182,3 +182,21 @@ def test_repeatable_bitwise(rq):
     f2 = rq.factor(_dev(a), 100, 32, 8, seed=9)
     assert np.array_equal(_np(f1.a), _np(f2.a))
     assert np.array_equal(_np(f1.b), _np(f2.b))
+
+
+def test_form_q_zero_tau_and_wide_block(rq):
+    """Explicit Q1 from the GPU's reflectors against the oracle's product of
+    reflectors: a rank-deficient input (tau = 0 past the rank, whose reflectors
+    are the identity) with 16-wide blocks, and a 128-wide block."""
+    a = np.zeros((120, 90))
+    a[:, :13] = gaussian(120, 13, 9)
+    f = rq.factor(_dev(a), 40, 8, 8, seed=3)
+    assert np.all(_np(f.tau)[13:] == 0.0)
+    q = _np(rq.form_q(f.a, f.tau, 40, 16))
+    qf = R.form_q(_np(f.a), _np(f.tau), 120)[:, :40]
+    assert np.abs(q - qf).max() <= 1e-13
+    a2 = gaussian(300, 200, 4)
+    f2 = rq.factor(_dev(a2), 150, 128, 8, seed=1)
+    q2 = _np(rq.form_q(f2.a, f2.tau, 150, 128))
+    qf2 = R.form_q(_np(f2.a), _np(f2.tau), 300)[:, :150]
+    assert np.abs(q2 - qf2).max() <= 1e-13

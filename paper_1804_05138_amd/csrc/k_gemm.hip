@@ -186,7 +186,8 @@ __global__ void k_extract_v(int rows, int bb, const T* __restrict__ a, long long
 // and dropping its index from M = T^-1 leaves the other entries unchanged.
 // One workgroup: row r of [M | I] in lane r of every wave, wave w holding
 // columns 16w .. 16w+15 of the inverse; backward elimination with the pivot
-// row of each wave's slice taken from lane j by readlane (no barrier per step).
+// row of each wave's slice taken from lane j by readlane (no barrier per step);
+// each lane stores its row once it is final.
 // The recurrence itself, for blocks wider than 64 (one workgroup, FP64).
 template <typename T>
 __global__ void k_larft_seq(int bb, const T* __restrict__ gm, const double* __restrict__ tau,
@@ -232,18 +233,19 @@ __global__ __launch_bounds__(256) void k_larft(int bb, const T* __restrict__ gm,
 #pragma unroll
   for (int i = 0; i < 16; ++i) a[i] = (r == 16 * w + i) ? 1.0 : 0.0;
   for (int j = bb - 1; j >= 0; --j) {
-    const double inv = 1.0 / sM[j * P + j];
-    const double mult = (r < j) ? sM[j * P + r] * inv : 0.0;
-    if (r == j) {
-      const bool lj = sTau[j] != 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int c = 16 * w + i;
-        if (c < bb) tm[c * bb + j] = (c >= j && lj && sTau[c] != 0.0) ? (T)(a[i] * inv) : T(0);
-      }
-    }
+    const double mult = (r < j) ? sM[j * P + r] / sM[j * P + j] : 0.0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+  }
+  // row r is final since step r (later steps only touch the rows above their pivot)
+  if (r < bb) {
+    const double inv = 1.0 / sM[r * P + r];
+    const bool lr = sTau[r] != 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int c = 16 * w + i;
+      if (c < bb) tm[c * bb + r] = (c >= r && lr && sTau[c] != 0.0) ? (T)(a[i] * inv) : T(0);
+    }
   }
 }
 

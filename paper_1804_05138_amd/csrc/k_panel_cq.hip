@@ -184,7 +184,7 @@ RQ_DEV void pad_identity(double* m, int bb) {
 // Cholesky G = R^T R of the symmetric g (bb x bb) and R^-1 in one symmetric
 // elimination of [G | I]: row j of the left half over sqrt(pivot) is row j of
 // R, row j of the right half over sqrt(pivot) is row j of R^-T.  Rows are
-// stored unscaled during the sweep and scaled at the end.  rout and rinv get
+// stored unscaled after the sweep and scaled at the end.  rout and rinv get
 // identity padding; rinv may be g.  Returns false if a pivot is not positive
 // and finite; dmin/dmax are the extreme pivots (diag(R)^2).  scol: 2 CB
 // doubles of LDS, sd: CB.
@@ -213,16 +213,6 @@ RQ_DEV bool chol_inv_pass(const double* g, double* rout, double* rinv, int bb, d
       if (j >= bb) break;
       double* sc = scol + (j & 1) * CB;
       if (w == jb / CW) sc[r] = a[jj];   // column j (G symmetric: also row j)
-      if (r == j) {                      // row j is final: store it unscaled
-#pragma unroll
-        for (int i = 0; i < CW; ++i) {
-          const int c = CW * w + i, cl = c & (CB - 1);
-          if (cl < bb) {
-            if (c < CB) rout[cl * CP + j] = a[i];
-            else rinv[j * CP + cl] = a[i];   // R^-T(j, cl) = R^-1(cl, j)
-          }
-        }
-      }
       __syncthreads();
       const double d = sc[j];
       const bool good = (d > 1e-300) && (d < 1e300);
@@ -234,6 +224,18 @@ RQ_DEV bool chol_inv_pass(const double* g, double* rout, double* rinv, int bb, d
       if (threadIdx.x == 0) sd[j] = dd;
 #pragma unroll
       for (int i = 0; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+    }
+  }
+  // row r stopped changing at step r (later steps only touch rows below their
+  // pivot): store the rows unscaled
+  if (r < bb) {
+#pragma unroll
+    for (int i = 0; i < CW; ++i) {
+      const int c = CW * w + i, cl = c & (CB - 1);
+      if (cl < bb) {
+        if (c < CB) rout[cl * CP + r] = a[i];
+        else rinv[r * CP + cl] = a[i];   // R^-T(r, cl) = R^-1(cl, r)
+      }
     }
   }
   __syncthreads();
@@ -273,16 +275,6 @@ RQ_DEV void lu_pass(const double* am, double* uout, double* linv, double* __rest
       if (j >= bb) break;
       double* sc = scol + (j & 1) * CB;
       if (w == jb / CW) sc[r] = a[jj];   // column j
-      if (r == j) {                      // row j is final
-#pragma unroll
-        for (int i = 0; i < CW; ++i) {
-          const int c = CW * w + i, cl = c & (CB - 1);
-          if (cl < bb) {
-            if (c < CB) uout[cl * CP + j] = a[i];
-            else linv[cl * CP + j] = a[i];   // L^-1(j, cl)
-          }
-        }
-      }
       __syncthreads();
       const double p = sc[j];
       const double st = (p >= 0.0) ? -1.0 : 1.0;
@@ -295,6 +287,16 @@ RQ_DEV void lu_pass(const double* am, double* uout, double* linv, double* __rest
       }
 #pragma unroll
       for (int i = 0; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+    }
+  }
+  if (r < bb) {   // final rows (as in chol_inv_pass)
+#pragma unroll
+    for (int i = 0; i < CW; ++i) {
+      const int c = CW * w + i, cl = c & (CB - 1);
+      if (cl < bb) {
+        if (c < CB) uout[cl * CP + r] = a[i];
+        else linv[cl * CP + r] = a[i];   // L^-1(r, cl)
+      }
     }
   }
   __syncthreads();
@@ -318,15 +320,17 @@ RQ_DEV void upper_inv_pass(const double* um, double* xout, int bb) {
   for (int j = bb - 1; j >= 0; --j) {
     const double inv = recip(um[j * CP + j]);
     const double mult = (r < j) ? um[j * CP + r] * inv : 0.0;
-    if (r == j) {
-#pragma unroll
-      for (int i = 0; i < CW; ++i) {
-        const int c = CW * w + i;
-        if (c < bb) xout[c * CP + j] = a[i] * inv;   // U^-1(j, c), zero for c < j
-      }
-    }
 #pragma unroll
     for (int i = 0; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+  }
+  // row r is final since step r (later steps touch rows above their pivot only)
+  if (r < bb) {
+    const double inv = recip(um[r * CP + r]);
+#pragma unroll
+    for (int i = 0; i < CW; ++i) {
+      const int c = CW * w + i;
+      if (c < bb) xout[c * CP + r] = a[i] * inv;   // U^-1(r, c), zero for c < r
+    }
   }
 }
 

@@ -154,9 +154,8 @@ __global__ __launch_bounds__(CT) void k_cq_sum(int nparts, const double* __restr
 // ---- small dense steps on CB x CB matrices (LDS by columns, pitch CP) ----
 // One workgroup of ST threads.  The eliminations keep row r of an augmented
 // matrix in lane r of every wave, wave w holding a slice of its columns in
-// registers.  Each wave takes the pivot row of its own slice from lane j with
-// readlane; only the multiplier column crosses waves, through LDS, with one
-// block barrier per step (the column buffer alternates between two halves).
+// registers; each wave takes pivot rows of its own slice from lane j with
+// readlane, and only multipliers cross waves, through LDS.
 
 constexpr int ST = 1024;      // threads of the small-matrix kernels
 constexpr int SW = ST / 64;   // their waves
@@ -181,16 +180,23 @@ RQ_DEV void pad_identity(double* m, int bb) {
   }
 }
 
+// The eliminations below run in blocks of CW steps, the CW columns of one
+// wave: that wave factors its own columns in registers (the multipliers of a
+// step are its own column over the pivot, the pivot row comes from lane j by
+// readlane), publishes the CW multiplier columns in LDS, and after one block
+// barrier every other wave applies the CW steps to its columns in order.  One
+// barrier per CW steps; the multiplier buffer alternates between two halves.
+constexpr int EW = 2 * CB / SW;   // columns of an augmented [M | I] per wave
+
 // Cholesky G = R^T R of the symmetric g (bb x bb) and R^-1 in one symmetric
 // elimination of [G | I]: row j of the left half over sqrt(pivot) is row j of
-// R, row j of the right half over sqrt(pivot) is row j of R^-T.  Rows are
-// stored unscaled after the sweep and scaled at the end.  rout and rinv get
-// identity padding; rinv may be g.  Returns false if a pivot is not positive
-// and finite; dmin/dmax are the extreme pivots (diag(R)^2).  scol: 2 CB
-// doubles of LDS, sd: CB.
-RQ_DEV bool chol_inv_pass(const double* g, double* rout, double* rinv, int bb, double* scol,
-                          double* sd, double& dmin, double& dmax) {
-  constexpr int CW = 2 * CB / SW;   // columns of [G | I] per wave
+// R, row j of the right half over sqrt(pivot) is row j of R^-T.  rout and
+// rinv get identity padding; rinv may be g.  Returns false if a pivot is not
+// positive and finite; dmin/dmax are the extreme pivots (diag(R)^2).
+// LDS: smult 2 EW 64 doubles, sd and sraw CB each.
+RQ_DEV bool chol_inv_pass(const double* g, double* rout, double* rinv, int bb, double* smult,
+                          double* sd, double* sraw, double& dmin, double& dmax) {
+  constexpr int CW = EW;
   const int r = threadIdx.x & 63, w = wave_index();
   double a[CW];
 #pragma unroll
@@ -202,28 +208,39 @@ RQ_DEV bool chol_inv_pass(const double* g, double* rout, double* rinv, int bb, d
   pad_identity(rout, bb);
   pad_identity(rinv, bb);
   __syncthreads();
-  bool ok = true;
-  dmin = 1e300;
-  dmax = 0.0;
-  // unrolled by CW so that column j sits at a fixed register of its owner wave
   for (int jb = 0; jb < bb; jb += CW) {
+    const int owner = jb / CW;
+    double* sm = smult + (owner & 1) * CW * 64;
+    if (w == owner) {
 #pragma unroll
-    for (int jj = 0; jj < CW; ++jj) {
-      const int j = jb + jj;
-      if (j >= bb) break;
-      double* sc = scol + (j & 1) * CB;
-      if (w == jb / CW) sc[r] = a[jj];   // column j (G symmetric: also row j)
-      __syncthreads();
-      const double d = sc[j];
-      const bool good = (d > 1e-300) && (d < 1e300);
-      ok = ok && good;
-      dmin = fmin(dmin, d);
-      dmax = fmax(dmax, d);
-      const double dd = good ? d : 1.0;
-      const double mult = (r > j && r < bb) ? sc[r] * recip(dd) : 0.0;
-      if (threadIdx.x == 0) sd[j] = dd;
+      for (int s = 0; s < CW; ++s) {
+        const int j = jb + s;
+        if (j < bb) {
+          const double d = readlane_f64(a[s], j);
+          const bool good = (d > 1e-300) && (d < 1e300);
+          const double dd = good ? d : 1.0;
+          const double mult = (r > j && r < bb) ? a[s] * recip(dd) : 0.0;
+          sm[s * 64 + r] = mult;
+          if (r == 0) {
+            sd[j] = dd;
+            sraw[j] = d;
+          }
 #pragma unroll
-      for (int i = 0; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+          for (int i = s + 1; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+        }
+      }
+    }
+    __syncthreads();
+    if (w != owner) {
+#pragma unroll
+      for (int s = 0; s < CW; ++s) {
+        const int j = jb + s;
+        if (j < bb) {
+          const double mult = sm[s * 64 + r];
+#pragma unroll
+          for (int i = 0; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+        }
+      }
     }
   }
   // row r stopped changing at step r (later steps only touch rows below their
@@ -245,6 +262,15 @@ RQ_DEV bool chol_inv_pass(const double* g, double* rout, double* rinv, int bb, d
     rout[c * CP + q] = (c >= q) ? rout[c * CP + q] * s : 0.0;   // R(q, c)
     rinv[q * CP + c] = (c <= q) ? rinv[q * CP + c] * s : 0.0;   // R^-1(c, q)
   }
+  bool ok = true;
+  dmin = 1e300;
+  dmax = 0.0;
+  for (int j = 0; j < bb; ++j) {
+    const double d = sraw[j];
+    ok = ok && (d > 1e-300) && (d < 1e300);
+    dmin = fmin(dmin, d);
+    dmax = fmax(dmax, d);
+  }
   return ok;
 }
 
@@ -252,11 +278,10 @@ RQ_DEV bool chol_inv_pass(const double* g, double* rout, double* rinv, int bb, d
 // = + (the pivot is the current diagonal entry before s_j is taken off), run
 // on [A | I]: uout = U, linv = L^-1 (both identity padded), L's strict lower
 // part to l1g (global, CB x CB by columns; the caller zeroes the rest), s_j to
-// s_s.  The multipliers of step j come from column j, published by the wave
-// owning it.  udg: CB doubles of LDS.
+// s_s.  Blocked as chol_inv_pass.  LDS: smult 2 EW 64 doubles, udg CB.
 RQ_DEV void lu_pass(const double* am, double* uout, double* linv, double* __restrict__ l1g,
-                    int bb, double* scol, double* s_s, double* udg) {
-  constexpr int CW = 2 * CB / SW;
+                    int bb, double* smult, double* s_s, double* udg) {
+  constexpr int CW = EW;
   const int r = threadIdx.x & 63, w = wave_index();
   double a[CW];
 #pragma unroll
@@ -269,24 +294,39 @@ RQ_DEV void lu_pass(const double* am, double* uout, double* linv, double* __rest
   pad_identity(linv, bb);
   __syncthreads();
   for (int jb = 0; jb < bb; jb += CW) {
+    const int owner = jb / CW;
+    double* sm = smult + (owner & 1) * CW * 64;
+    if (w == owner) {
 #pragma unroll
-    for (int jj = 0; jj < CW; ++jj) {
-      const int j = jb + jj;
-      if (j >= bb) break;
-      double* sc = scol + (j & 1) * CB;
-      if (w == jb / CW) sc[r] = a[jj];   // column j
-      __syncthreads();
-      const double p = sc[j];
-      const double st = (p >= 0.0) ? -1.0 : 1.0;
-      const double utt = p - st;   // |utt| >= 1
-      const double mult = (r > j && r < bb) ? sc[r] * recip(utt) : 0.0;
-      if (w == 0 && r > j && r < bb) l1g[j * CB + r] = mult;
-      if (threadIdx.x == 0) {
-        s_s[j] = st;
-        udg[j] = utt;
+      for (int s = 0; s < CW; ++s) {
+        const int j = jb + s;
+        if (j < bb) {
+          const double p = readlane_f64(a[s], j);
+          const double st = (p >= 0.0) ? -1.0 : 1.0;
+          const double utt = p - st;   // |utt| >= 1
+          const double mult = (r > j && r < bb) ? a[s] * recip(utt) : 0.0;
+          sm[s * 64 + r] = mult;
+          if (r > j && r < bb) l1g[j * CB + r] = mult;
+          if (r == 0) {
+            s_s[j] = st;
+            udg[j] = utt;
+          }
+#pragma unroll
+          for (int i = s + 1; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+        }
       }
+    }
+    __syncthreads();
+    if (w != owner) {
 #pragma unroll
-      for (int i = 0; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+      for (int s = 0; s < CW; ++s) {
+        const int j = jb + s;
+        if (j < bb) {
+          const double mult = sm[s * 64 + r];
+#pragma unroll
+          for (int i = 0; i < CW; ++i) a[i] = fma(-mult, readlane_f64(a[i], j), a[i]);
+        }
+      }
     }
   }
   if (r < bb) {   // final rows (as in chol_inv_pass)
@@ -371,14 +411,15 @@ __global__ __launch_bounds__(ST) void k_cq_chol1(int bb, const double* __restric
                                                  double* __restrict__ r1,
                                                  double* __restrict__ r1inv,
                                                  int* __restrict__ flag) {
-  __shared__ double scol[2 * CB];
+  __shared__ double smult[2 * EW * 64];
   __shared__ double sd[CB];
+  __shared__ double sraw[CB];
   __shared__ double sG[CB * CP];   // G1, then R1^-1
   __shared__ double sR[CB * CP];
   stage_small<ST>(g1, sG);   // G1 is symmetric: its rows are its columns
   __syncthreads();
   double dmin, dmax;
-  const bool ok = chol_inv_pass(sG, sR, sG, bb, scol, sd, dmin, dmax);
+  const bool ok = chol_inv_pass(sG, sR, sG, bb, smult, sd, sraw, dmin, dmax);
   __syncthreads();
   // usable if every pivot is positive and finite and diag(R1) spreads less than 1e6
   if (threadIdx.x == 0) *flag = (ok && dmin > 1e-12 * dmax) ? 1 : 0;
@@ -469,9 +510,10 @@ __global__ __launch_bounds__(ST) void k_cq_small(int bb, const double* __restric
                                                  double* __restrict__ tmat,
                                                  double* __restrict__ tau,
                                                  int* __restrict__ flag) {
-  __shared__ double scol[2 * CB];
+  __shared__ double smult[2 * EW * 64];
   __shared__ double s_s[CB];
   __shared__ double sd[CB];
+  __shared__ double sraw[CB];
   __shared__ double P0[CB * CP];
   __shared__ double P1[CB * CP];
   __shared__ double P2[CB * CP];
@@ -503,7 +545,7 @@ __global__ __launch_bounds__(ST) void k_cq_small(int bb, const double* __restric
   }
   __syncthreads();
   double dmin, dmax;
-  const bool ok = chol_inv_pass(P0, P3, P0, bb, scol, sd, dmin, dmax);   // R2 -> P3, R2^-1 -> P0
+  const bool ok = chol_inv_pass(P0, P3, P0, bb, smult, sd, sraw, dmin, dmax);   // R2 -> P3, R2^-1 -> P0
   __syncthreads();
   const v4d rh0 = mm_tile(P3, [&](int k, int c) { return P1[c * CP + k]; });   // R2 R1
   const v4d qt = mm_tile(P2, [&](int k, int c) { return P0[c * CP + k]; });    // Q1top R2^-1
@@ -511,7 +553,7 @@ __global__ __launch_bounds__(ST) void k_cq_small(int bb, const double* __restric
 #pragma unroll
   for (int e = 0; e < 4; ++e) P1[(16 * cb + l16) * CP + 16 * rb + acc_row<double>(lg, e)] = qt[e];
   __syncthreads();
-  lu_pass(P1, P2, P3, l1out, bb, scol, s_s, sd);   // U -> P2, L1^-1 -> P3
+  lu_pass(P1, P2, P3, l1out, bb, smult, s_s, sd);   // U -> P2, L1^-1 -> P3
   __syncthreads();
   upper_inv_pass(P2, P1, bb);                     // U^-1 -> P1
   __syncthreads();

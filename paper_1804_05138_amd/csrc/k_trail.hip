@@ -119,7 +119,16 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail(
   fetch_a(ri0, d);
   for (int r0 = ri0; r0 < ri1; r0 += TR) {
     // ---- stage this tile's reflector rows (fetched one tile ahead) ----
-    {
+    // Tiles below both diagonal blocks, inside the matrix and with full-width
+    // blocks need no masking (the common case, a uniform branch).
+    if (r0 >= in + bbn && r0 + TR <= m && bbu == BBM && bbn == BBM) {
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) {
+        const int q = q0 + QS * j;
+        sVuT[q * TR + (rr ^ ((q & 1) << 4))] = pu[j];
+        sVn[rr * BBM + (q ^ swz_n(rr))] = pn[j];
+      }
+    } else {
       // flat selects (no branches): zero outside the block width and past row m,
       // so partial blocks run the full-width MFMA loop on zero padding
       const int r = r0 + rr;
@@ -170,11 +179,12 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail(
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int r = 16 * b + acc_row<T>(lg, e);
+          // all operands of this row first, then the MFMAs (one LDS wait)
+          T av[BBM / 16];
 #pragma unroll
-          for (int qb = 0; qb < BBM / 16; ++qb) {
-            const T av = sVn[r * BBM + ((16 * qb + lr16) ^ swz_n(r))];
-            acc[qb] = TrailMfma<T>::run(av, d[b][e], acc[qb]);
-          }
+          for (int qb = 0; qb < BBM / 16; ++qb) av[qb] = sVn[r * BBM + ((16 * qb + lr16) ^ swz_n(r))];
+#pragma unroll
+          for (int qb = 0; qb < BBM / 16; ++qb) acc[qb] = TrailMfma<T>::run(av[qb], d[b][e], acc[qb]);
         }
     }
     __syncthreads();

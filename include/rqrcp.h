@@ -55,6 +55,7 @@ typedef struct rqrcp_ctx *rqrcp_handle;
 #define RQRCP_ERR_DEVICE 1004      /* the current device is not gfx950 */
 #define RQRCP_ERR_LIMIT 1005       /* size beyond what the kernels accept (see rqrcp_limits) */
 #define RQRCP_ERR_BARRIER 1006     /* a persistent kernel's grid barrier timed out */
+#define RQRCP_ERR_NUMERIC 1007     /* the sketch held a non-finite value: no pivot could be chosen */
 
 /* Element types.  A may be FP64 or FP32; the sketch B, Omega, tau and all
  * reflector arithmetic are FP64.  The sketch product may run in FP64, BF16 or
@@ -218,7 +219,8 @@ int rqrcp_batched_workspace_size(size_t *bytes);
 /* Factor `batch` problems in place (A_j -> R, V, R22 in LAPACK storage).
  * prm: a_type = RQRCP_F32, sketch_type = RQRCP_F64, b, p, seed.  *_elems are the
  * pool sizes in elements; a problem whose descriptor does not fit the kernel's
- * limits or the pools is skipped with info[j] = -1.  info[j] otherwise as in
+ * limits or the pools is skipped with info[j] = -1; a sketch with a non-finite
+ * value stops that problem's pivoting with info[j] = -2.  info[j] otherwise as in
  * rqrcp_factor.  The kernel variant comes from the library's tuning table
  * (rqrcp_autotune_batched; one per device, shared by all handles of the
  * process), default variant 0. */
@@ -240,10 +242,12 @@ int rqrcp_autotune_batched(rqrcp_handle h, int batch, const rqrcp_problem *probs
                            void *ws, size_t ws_bytes, const float *A_orig, int *best_variant,
                            float *ms_per_variant);
 
-/* Synchronizes the handle's stream and returns RQRCP_ERR_BARRIER if a
- * persistent kernel reported a barrier timeout since the last check (and
- * clears the flag), RQRCP_ERR_HIP on a HIP error, else 0.  `ws` is the
- * workspace the kernels ran with. */
+/* Synchronizes the handle's stream and returns RQRCP_ERR_NUMERIC if the sketch
+ * QRCP found no valid pivot (a non-finite sketch; it stops pivoting, and the
+ * factorization is not usable), RQRCP_ERR_BARRIER if a persistent kernel
+ * reported a barrier timeout since the last check (both flags are cleared),
+ * RQRCP_ERR_HIP on a HIP error, else 0.  `ws` is the workspace the kernels ran
+ * with. */
 int rqrcp_check(rqrcp_handle h, void *ws);
 
 /* Per-phase timing for benchmarks.  While enabled, rqrcp_factor and

@@ -796,7 +796,8 @@ int rqrcp_check(rqrcp_handle h, void* ws) {
     const unsigned zero[3] = {0, 0, 0};
     hipMemcpy(w + QSCR_OFF, zero, sizeof(zero), hipMemcpyHostToDevice);
     hipMemcpy(w + PSCR_OFF, zero, sizeof(zero), hipMemcpyHostToDevice);
-    return RQRCP_ERR_BARRIER;
+    // bit 1 of the sketch QRCP's word: no valid pivot (a non-finite sketch)
+    return (bars[0].err & 2u) ? RQRCP_ERR_NUMERIC : RQRCP_ERR_BARRIER;
   }
   return 0;
 }
@@ -845,6 +846,7 @@ const char* rqrcp_status_string(int status) {
     case RQRCP_ERR_DEVICE: return "device is not gfx950";
     case RQRCP_ERR_LIMIT: return "size beyond the kernels' limits";
     case RQRCP_ERR_BARRIER: return "grid barrier timed out";
+    case RQRCP_ERR_NUMERIC: return "non-finite value in the sketch (no pivot could be chosen)";
     default: return "unknown status";
   }
 }

@@ -180,11 +180,13 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
           }
         }
         block_argmax_pos<NT>(bn, bp, S.red, reinterpret_cast<int*>(S.red + 8 * BMAX));
-        if (uniform_i(bn == 0.0 ? 1 : 0)) {
-          // exact zero sketch: no more pivots, no more sketch updates
+        // no finite candidate (a NaN in the sketch) or an exact zero sketch: no
+        // more pivots, no more sketch updates (info -2 or the rank + 1)
+        const bool nonfinite = !(bn >= 0.0) || bp < gpos || bp >= n;
+        if (uniform_i((bn == 0.0 || nonfinite) ? 1 : 0)) {
           if (tid == 0) {
             S.dead = 1;
-            S.info = gpos + 1;
+            S.info = nonfinite ? -2 : gpos + 1;
           }
           __syncthreads();
           continue;

@@ -190,6 +190,15 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
       __syncthreads();
       wcol = colbuf;
     }
+    // A winner that is not a column of this block (no candidate norm is a
+    // finite nonnegative number, e.g. a NaN in the sketch) must not steer the
+    // bookkeeping or the write-back: flag it and keep the column already at
+    // position t (no move); the factorization is then reported unusable.
+    if (!(gn >= 0.0) || jpos < 0 || jpos >= nc || wslot < 0 || wslot >= nc) {
+      if (g == 0 && tid == 0) atomicOr(&bar->err, 2u);
+      jpos = t;
+      wslot = q_at_t;
+    }
     // dlarfg on the winner's rows t..l-1 (every wave, same order, same result)
     double xn2 = 0.0;
     for (int r = t + 1 + lane; r < l; r += 64) xn2 += wcol[r] * wcol[r];

@@ -387,12 +387,12 @@ int rqrcp_set_stream(rqrcp_handle h, void* stream) {
 int rqrcp_limits(int l, int* max_b, int* max_l, int* max_n) {
   if (max_b) *max_b = MAX_B;
   if (max_l) *max_l = MAX_L;
-  // 256 sketch columns per workgroup, one workgroup per compute unit
+  // the sketch QRCP's grid (256 columns per workgroup, 128 for l > 80) at
+  // one workgroup per compute unit
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)l;
-  if (max_n) *max_n = 256 * ncu;
+  if (max_n) *max_n = (l > 80 ? 128 : 256) * ncu;
   return 0;
 }
 

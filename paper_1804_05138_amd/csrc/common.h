@@ -271,7 +271,8 @@ RQ_DEV double readlane_f64(double v, int lane) {
 // DPP controls (GCN/CDNA encoding)
 constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114,
               DPP_ROW_SHR8 = 0x118, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143,
-              DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+              DPP_QUAD_XOR1 = 0xB1,  // quad_perm [1,0,3,2]
+              DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
 
 // Sum over the wave, returned in every lane.  The summation order is fixed.
 RQ_DEV double wave_sum_dpp(double v) {
@@ -287,6 +288,12 @@ RQ_DEV double wave_sum_dpp(double v) {
 // Sum of adjacent lane pairs (lane ^ 1), returned in both lanes.
 RQ_DEV double pair_sum_dpp(double v) {
   return v + dpp_f64<DPP_QUAD_XOR1, 0xf, 0xf, false>(v, v);
+}
+
+// Sum over each quad of lanes (lane ^ 1, lane ^ 2), returned in all four.
+RQ_DEV double quad_sum_dpp(double v) {
+  v = pair_sum_dpp(v);
+  return v + dpp_f64<DPP_QUAD_XOR2, 0xf, 0xf, false>(v, v);
 }
 
 // Arg-max over the wave of (n, then lowest p); s is carried along.  The

@@ -27,11 +27,13 @@ namespace {
 template <int TPC>
 RQ_DEV double tpc_sum(double v) {
   if constexpr (TPC == 2) v = pair_sum_dpp(v);
+  if constexpr (TPC == 4) v = quad_sum_dpp(v);
   return v;
 }
 
-// QT threads per workgroup; every workgroup holds CPW = QT / TPC = 256 columns,
-// each column split over TPC threads (rows sub, sub + TPC, ...).
+// QT threads per workgroup; every workgroup holds CPW = QT / TPC columns (256,
+// or 128 for the tallest sketches), each column split over TPC threads (rows
+// sub, sub + TPC, ...).
 template <int RPT, int TPC, int QT>
 __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
     double* __restrict__ bsk, long long ldb, int l, int nc, int nsteps, int gstep0,
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
 template <int RPT, int TPC>
 int launch_t(hipStream_t s, double* b, long long ldb, int l, int nc, int nsteps, int gstep0,
              QrcpScratch* scr, double* cand, int* pairs, int* info) {
-  constexpr int QT = 256 * TPC;
+  constexpr int QT = TPC == 4 ? 512 : 256 * TPC;   // at most 512 threads: room for x[RPT]
   constexpr int CPW = QT / TPC;
   auto kern = &k_qrcp_sketch<RPT, TPC, QT>;
   const int G = (nc + CPW - 1) / CPW;
@@ -306,14 +308,15 @@ int launch_t(hipStream_t s, double* b, long long ldb, int l, int nc, int nsteps,
 }  // namespace
 
 size_t qrcp_cand_doubles(int l, int nc) {
-  const size_t G = (size_t)(nc + 255) / 256;
+  const size_t cpw = l > 80 ? 128 : 256;
+  const size_t G = ((size_t)nc + cpw - 1) / cpw;
   const size_t cs = ((l + 4) + 7) / 8 * 8;
   return 2 * G * cs;
 }
 
 int qrcp_sketch_grid(int l, int nc) {
-  (void)l;
-  return (nc + 255) / 256;
+  const int cpw = l > 80 ? 128 : 256;
+  return (nc + cpw - 1) / cpw;
 }
 
 int launch_qrcp_sketch(hipStream_t s, double* b, long long ldb, int l, int c0, int nc, int nsteps,
@@ -324,7 +327,7 @@ int launch_qrcp_sketch(hipStream_t s, double* b, long long ldb, int l, int c0, i
   if (l <= 32) return launch_t<32, 1>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
   if (l <= 48) return launch_t<48, 1>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
   if (l <= 80) return launch_t<40, 2>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
-  return launch_t<80, 2>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
+  return launch_t<40, 4>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
 }
 
 }  // namespace rq

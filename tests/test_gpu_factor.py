@@ -103,6 +103,7 @@ def test_sketch_with_user_omega(rq):
     (700, 300, 96, 32, 8),     # tall, several row tiles
     (256, 256, 256, 64, 8),    # k = n: full factorization
     (97, 131, 97, 13, 5),      # k = m < n, odd block size
+    (500, 400, 160, 80, 16),   # tall sketch (l = 96): four columns per thread, several workgroups
 ])
 def test_factor_parity(rq, m, n, k, b, p):
     a = separated_lowrank(m, n, 11)

@@ -79,6 +79,19 @@ template <typename T>
 int launch_panel_cq(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
                     const double* wp, long long ldw, double* tau, double* tmat, double* scratch,
                     int* flag);
+// Pieces for blocks wider than 64 (two 64-wide halves): the pending update of
+// columns i+coff .. i+coff+nc, C = A^T B (CB x CB, fixed-order sum), W' =
+// T1^T Y and the T of the whole block.
+template <typename T>
+int launch_cq_pend(hipStream_t s, int m, T* a, long long lda, int i, int coff, int nc, int bbp,
+                   const double* wp, long long ldw);
+size_t cq_wide_doubles(int rows);
+template <typename T>
+int launch_cq_cross(hipStream_t s, int rows, const T* A, long long lda, int na, int adiag,
+                    const T* B, long long ldb, int nb, int bdiag, double* part, double* c);
+int launch_cq_tty(hipStream_t s, int nb, const double* t1, const double* y, double* w);
+int launch_cq_tcombine(hipStream_t s, int nb, const double* t1, const double* t2, const double* z,
+                       double* t);
 
 // Trailing pass over columns [c_begin, c_end) of A, rows [i, m):
 //   if bbu > 0:  A(i:m, c) -= V_i * Wp(:, c - w0)      (V_i = A(i:m, i:i+bbu) reflectors)

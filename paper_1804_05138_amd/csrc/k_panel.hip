@@ -477,7 +477,8 @@ static size_t stepwise_partial_doubles(int rows, int bb) {
 }
 
 size_t panel_partial_doubles(int rows, int bb) {
-  return stepwise_partial_doubles(rows, bb) + panel_cq_doubles(rows);
+  return stepwise_partial_doubles(rows, bb) + panel_cq_doubles(rows) +
+         (bb > 64 ? cq_wide_doubles(rows) : 0);
 }
 
 int panel_grid(int rows, int bb) {
@@ -551,10 +552,72 @@ int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int b
                  const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
                  double* partial) {
   if (bb < 1 || bb > MAX_B || bbp < 0 || bbp > MAX_B) return RQ_ERR_LIMIT;
+  // The previous block's pending update of columns i+coff .. i+coff+nc,
+  // A -= V_prev W', in rank-64 pieces: piece q0 is V_prev(:, q0:q0+qb), unit
+  // lower from row rp + q0, against rows q0.. of W'.
+  auto pend_all = [&](int coff, int nc) -> int {
+    const int rp = i - bbp;
+    for (int q0 = 0; q0 < bbp; q0 += 64) {
+      const int qb = bbp - q0 < 64 ? bbp - q0 : 64;
+      const int ie = rp + q0 + qb;      // the kernel's "panel start" for this piece
+      const int ce = i + coff - ie;     // target columns i + coff + c
+      const double* we = wp + q0 + (long long)(ie - i) * ldw;   // we[(ce + c) ldw + q] = W'(q0 + q, coff + c)
+      const int rc = launch_cq_pend<T>(s, m, a, lda, ie, ce, nc, qb, we, ldw);
+      if (rc) return rc;
+    }
+    return RQ_OK;
+  };
+  if (bb > 64 && panel_cq_applicable(m, i, 64) && panel_cq_applicable(m, i + 64, bb - 64)) {
+    // Two 64-wide halves by Cholesky-QR2 (each with the stepwise kernel as its
+    // fallback): factor the first, apply its reflectors to the second
+    // (X2 -= V1 T1^T V1^T X2), factor the second, and join the T factors,
+    // T = [[T1, -T1 (V1^T V2) T2], [0, T2]], for Q = Q1 Q2.
+    const int b2 = bb - 64;
+    double* cqs = partial + stepwise_partial_doubles(m - (i - bbp), bb);
+    double* wide = cqs + panel_cq_doubles(m - i);
+    double* part = wide;
+    double* t1 = part + cq_wide_doubles(m - i) - 5 * 64 * 64;
+    double* t2 = t1 + 64 * 64;
+    double* y = t2 + 64 * 64;
+    double* wq = y + 64 * 64;
+    double* z = wq + 64 * 64;
+    int rc;
+    if (bbp > 0) {
+      if ((rc = pend_all(0, 64))) return rc;
+      if ((rc = pend_all(64, b2))) return rc;
+    }
+    // first half
+    if ((rc = launch_panel_cq<T>(s, m, a, lda, i, 64, 0, nullptr, 0, tau, t1, cqs, scr->cq_flag)))
+      return rc;
+    if ((rc = launch_stepwise<T>(s, m, a, lda, i, 64, 0, nullptr, 0, tau, t1, scr, partial,
+                                 scr->cq_flag)))
+      return rc;
+    // X2 -= V1 (T1^T (V1^T X2)) over rows i .. m-1
+    const T* v1 = a + (long long)i * lda + i;
+    const T* x2 = a + (long long)(i + 64) * lda + i;
+    if ((rc = launch_cq_cross<T>(s, m - i, v1, lda, 64, 0, x2, lda, b2, -1, part, y))) return rc;
+    if ((rc = launch_cq_tty(s, b2, t1, y, wq))) return rc;
+    if ((rc = launch_cq_pend<T>(s, m, a, lda, i + 64, 0, b2, 64, wq, 64))) return rc;
+    // second half
+    if ((rc = launch_panel_cq<T>(s, m, a, lda, i + 64, b2, 0, nullptr, 0, tau, t2, cqs,
+                                 scr->cq_flag)))
+      return rc;
+    if ((rc = launch_stepwise<T>(s, m, a, lda, i + 64, b2, 0, nullptr, 0, tau, t2, scr, partial,
+                                 scr->cq_flag)))
+      return rc;
+    // Z = V1^T V2 over rows i+64 .. m-1, then T
+    const T* v1b = a + (long long)i * lda + i + 64;
+    const T* v2 = a + (long long)(i + 64) * lda + i + 64;
+    if ((rc = launch_cq_cross<T>(s, m - i - 64, v1b, lda, 64, -1, v2, lda, b2, 0, part, z)))
+      return rc;
+    return launch_cq_tcombine(s, b2, t1, t2, z, t);
+  }
   if (panel_cq_applicable(m, i, bb)) {
     // Cholesky-QR2 panel; the stepwise kernel runs only if that path declined
     double* cqs = partial + stepwise_partial_doubles(m - (i - bbp), bb);
-    int rc = launch_panel_cq<T>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, cqs, scr->cq_flag);
+    int rc;
+    if (bbp > 0 && (rc = pend_all(0, bb))) return rc;
+    rc = launch_panel_cq<T>(s, m, a, lda, i, bb, 0, nullptr, 0, tau, t, cqs, scr->cq_flag);
     if (rc) return rc;
     return launch_stepwise<T>(s, m, a, lda, i, bb, 0, nullptr, 0, tau, t, scr, partial,
                               scr->cq_flag);

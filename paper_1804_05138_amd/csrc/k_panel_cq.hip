@@ -34,11 +34,12 @@ constexpr int CP = CB + 1;    // LDS pitch
 constexpr int CR = 128;       // rows per workgroup of the row-parallel kernels
 constexpr int CT = 256;
 
-// ---- pending update A(rp:m, i:i+bb) -= V_prev W' (V_prev unit lower at column rp) ----
+// ---- pending update A(rp:m, i+coff : i+coff+bb) -= V_prev W'(:, coff : coff+bb)
+// (V_prev unit lower at column rp = i - bbp) ----
 template <typename T>
 __global__ __launch_bounds__(CT) void k_cq_pend(int m, T* __restrict__ a, long long lda, int i,
-                                                int bb, int bbp, const double* __restrict__ wp,
-                                                long long ldw) {
+                                                int coff, int bb, int bbp,
+                                                const double* __restrict__ wp, long long ldw) {
   __shared__ double sv[CR * CP];   // V_prev rows of this workgroup, [row][q]
   __shared__ double sw[CB * CP];   // W'(q, c) at sw[c * CP + q]
   const int rp = i - bbp;
@@ -53,12 +54,12 @@ __global__ __launch_bounds__(CT) void k_cq_pend(int m, T* __restrict__ a, long l
   }
   for (int e = tid; e < bb * bbp; e += CT) {
     const int c = e / bbp, q = e % bbp;
-    sw[c * CP + q] = wp[(long long)c * ldw + q];
+    sw[c * CP + q] = wp[(long long)(coff + c) * ldw + q];
   }
   __syncthreads();
   const int c = tid % CB, rg = tid / CB;
   if (c >= bb) return;
-  T* col = a + (long long)(i + c) * lda;
+  T* col = a + (long long)(i + coff + c) * lda;
   for (int rr = rg; rr < CR; rr += CT / CB) {
     const int r = r0 + rr;
     if (r >= m) break;
@@ -646,6 +647,98 @@ __global__ __launch_bounds__(CT) void k_cq_y(int rows, T* __restrict__ x, long l
   }
 }
 
+// ---- blocks wider than CB: two CB-wide halves and the T of the whole block ----
+
+// Partial C = A^T B (CB x CB) of a CR-row chunk on FP64 MFMA.  A and B have
+// na, nb <= CB columns; a nonnegative adiag/bdiag makes that operand the unit
+// lower trapezoid whose diagonal starts at that row (entries above it zero).
+template <typename T>
+__global__ __launch_bounds__(CT) void k_cq_cross(int rows, const T* __restrict__ A, long long lda,
+                                                 int na, int adiag, const T* __restrict__ B,
+                                                 long long ldb, int nb, int bdiag,
+                                                 double* __restrict__ part) {
+  __shared__ double sa[CR * CP];
+  __shared__ double sb[CR * CP];
+  const int r0 = blockIdx.x * CR;
+  for (int e = threadIdx.x; e < CR * CB; e += CT) {
+    const int c = e / CR, rr = e % CR, r = r0 + rr;
+    const bool in = r < rows;
+    double va = 0.0, vb = 0.0;
+    if (in && c < na) {
+      const double v = (double)A[(long long)c * lda + r];
+      va = (adiag < 0 || r - adiag > c) ? v : (r - adiag == c ? 1.0 : 0.0);
+    }
+    if (in && c < nb) {
+      const double v = (double)B[(long long)c * ldb + r];
+      vb = (bdiag < 0 || r - bdiag > c) ? v : (r - bdiag == c ? 1.0 : 0.0);
+    }
+    sa[rr * CP + c] = va;
+    sb[rr * CP + c] = vb;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  v4d acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int kk = 0; kk < CR / 4; ++kk) {
+    const int r = 4 * kk + lg;
+    const double av = sa[r * CP + 16 * wave + l16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = mfma_f64(av, sb[r * CP + 16 * t + l16], acc[t]);
+  }
+  double* out = part + (size_t)blockIdx.x * CB * CB;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      out[(16 * t + l16) * CB + 16 * wave + acc_row<double>(lg, e)] = acc[t][e];
+}
+
+// W' = T1^T Y (T1: CB x CB upper, ld CB; Y: CB x nb, ld CB; W': ld CB).
+__global__ __launch_bounds__(CT) void k_cq_tty(int nb, const double* __restrict__ t1,
+                                               const double* __restrict__ y,
+                                               double* __restrict__ w) {
+  for (int e = threadIdx.x; e < CB * nb; e += CT) {
+    const int c = e / CB, q = e % CB;
+    double acc = 0.0;
+    for (int p = 0; p <= q; ++p) acc += t1[q * CB + p] * y[c * CB + p];
+    w[c * CB + q] = acc;
+  }
+}
+
+// T of the whole block (bb = CB + nb, ld bb): [[T1, -T1 Z T2], [0, T2]] with
+// Z = V1^T V2 (CB x nb, ld CB), T1 (ld CB), T2 (nb x nb, ld nb).
+__global__ __launch_bounds__(CT) void k_cq_tcombine(int nb, const double* __restrict__ t1,
+                                                    const double* __restrict__ t2,
+                                                    const double* __restrict__ z,
+                                                    double* __restrict__ t) {
+  __shared__ double sm[CB * CB];   // Z T2
+  const int bb = CB + nb;
+  for (int e = threadIdx.x; e < CB * nb; e += CT) {
+    const int c = e / CB, p = e % CB;
+    double acc = 0.0;
+    for (int q = 0; q <= c; ++q) acc += z[q * CB + p] * t2[c * nb + q];
+    sm[c * CB + p] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < bb * bb; e += CT) {
+    const int c = e / bb, r = e % bb;
+    double v = 0.0;
+    if (c < CB) {
+      v = (r < CB) ? t1[c * CB + r] : 0.0;
+    } else if (r >= CB) {
+      v = t2[(c - CB) * nb + (r - CB)];
+    } else {
+      double acc = 0.0;
+      for (int s2 = r; s2 < CB; ++s2) acc += t1[s2 * CB + r] * sm[(c - CB) * CB + s2];
+      v = -acc;
+    }
+    t[e] = v;
+  }
+}
+
 }  // namespace
 
 size_t panel_cq_doubles(int rows) {
@@ -676,8 +769,8 @@ int launch_panel_cq(hipStream_t s, int m, T* a, long long lda, int i, int bb, in
   T* x = a + (long long)i * lda + i;
   if (bbp > 0) {
     const int prow = m - (i - bbp);
-    hipLaunchKernelGGL(k_cq_pend<T>, dim3((prow + CR - 1) / CR), dim3(CT), 0, s, m, a, lda, i, bb,
-                       bbp, wp, ldw);
+    hipLaunchKernelGGL(k_cq_pend<T>, dim3((prow + CR - 1) / CR), dim3(CT), 0, s, m, a, lda, i, 0,
+                       bb, bbp, wp, ldw);
   }
   hipLaunchKernelGGL(k_cq_gram<T>, dim3(nchunk), dim3(CT), 0, s, rows, (const T*)x, lda, bb, part,
                      (const int*)nullptr);
@@ -701,5 +794,56 @@ template int launch_panel_cq<double>(hipStream_t, int, double*, long long, int, 
                                      const double*, long long, double*, double*, double*, int*);
 template int launch_panel_cq<float>(hipStream_t, int, float*, long long, int, int, int,
                                     const double*, long long, double*, double*, double*, int*);
+
+template <typename T>
+int launch_cq_pend(hipStream_t s, int m, T* a, long long lda, int i, int coff, int nc, int bbp,
+                   const double* wp, long long ldw) {
+  if (nc < 1 || nc > CB || bbp < 1 || bbp > CB) return RQ_ERR_LIMIT;
+  const int prow = m - (i - bbp);
+  hipLaunchKernelGGL(k_cq_pend<T>, dim3((prow + CR - 1) / CR), dim3(CT), 0, s, m, a, lda, i, coff,
+                     nc, bbp, wp, ldw);
+  RQ_HIP_CHECK(hipGetLastError());
+  return RQ_OK;
+}
+template int launch_cq_pend<double>(hipStream_t, int, double*, long long, int, int, int, int,
+                                    const double*, long long);
+template int launch_cq_pend<float>(hipStream_t, int, float*, long long, int, int, int, int,
+                                   const double*, long long);
+
+size_t cq_wide_doubles(int rows) {
+  const size_t nchunk = (size_t)(rows + CR - 1) / CR;
+  return nchunk * CB * CB + 5 * (size_t)CB * CB;
+}
+
+// C = A^T B over `rows` rows (see k_cq_cross), summed in a fixed order into c
+// (CB x CB doubles, ld CB); part: cq_wide scratch.
+template <typename T>
+int launch_cq_cross(hipStream_t s, int rows, const T* A, long long lda, int na, int adiag,
+                    const T* B, long long ldb, int nb, int bdiag, double* part, double* c) {
+  const int nchunk = (rows + CR - 1) / CR;
+  hipLaunchKernelGGL(k_cq_cross<T>, dim3(nchunk), dim3(CT), 0, s, rows, A, lda, na, adiag, B, ldb,
+                     nb, bdiag, part);
+  hipLaunchKernelGGL(k_cq_sum, dim3(CB * CB / CT), dim3(CT), 0, s, nchunk, (const double*)part, c,
+                     (const int*)nullptr);
+  RQ_HIP_CHECK(hipGetLastError());
+  return RQ_OK;
+}
+template int launch_cq_cross<double>(hipStream_t, int, const double*, long long, int, int,
+                                     const double*, long long, int, int, double*, double*);
+template int launch_cq_cross<float>(hipStream_t, int, const float*, long long, int, int,
+                                    const float*, long long, int, int, double*, double*);
+
+int launch_cq_tty(hipStream_t s, int nb, const double* t1, const double* y, double* w) {
+  hipLaunchKernelGGL(k_cq_tty, dim3(1), dim3(CT), 0, s, nb, t1, y, w);
+  RQ_HIP_CHECK(hipGetLastError());
+  return RQ_OK;
+}
+
+int launch_cq_tcombine(hipStream_t s, int nb, const double* t1, const double* t2, const double* z,
+                       double* t) {
+  hipLaunchKernelGGL(k_cq_tcombine, dim3(1), dim3(CT), 0, s, nb, t1, t2, z, t);
+  RQ_HIP_CHECK(hipGetLastError());
+  return RQ_OK;
+}
 
 }  // namespace rq

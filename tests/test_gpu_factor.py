@@ -104,6 +104,8 @@ def test_sketch_with_user_omega(rq):
     (256, 256, 256, 64, 8),    # k = n: full factorization
     (97, 131, 97, 13, 5),      # k = m < n, odd block size
     (500, 400, 160, 80, 16),   # tall sketch (l = 96): four columns per thread, several workgroups
+    (400, 300, 150, 128, 8),   # a 128-wide panel in two halves, then a narrow one after it
+    (600, 500, 256, 128, 16),  # 128-wide panels after 128-wide blocks
 ])
 def test_factor_parity(rq, m, n, k, b, p):
     a = separated_lowrank(m, n, 11)

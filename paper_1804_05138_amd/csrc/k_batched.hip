@@ -140,6 +140,8 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
         }
         __syncthreads();
         const int rn = min(RC, m - r0);
+        // rows in groups so that their loads are in flight together
+#pragma unroll 16
         for (int rr = 0; rr < rn; ++rr) {
           const double av = cok ? (double)acol[r0 + rr] : 0.0;
 #pragma unroll
@@ -401,6 +403,7 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
           if (cok) {
             const int rb = i + NT * u;
             const int rn = min(NT, m - rb);
+#pragma unroll 32
             for (int rr = 0; rr < rn; ++rr) {
               const float av = acol[rb + rr];
 #pragma unroll
@@ -435,6 +438,7 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
           if (cok) {
             const int rb = i + NT * u;
             const int rn = min(NT, m - rb);
+#pragma unroll 32
             for (int rr = 0; rr < rn; ++rr) {
               float x = acol[rb + rr];
 #pragma unroll

@@ -112,7 +112,8 @@ size_t wpart_doubles(int m, int n, int k, int b) {
   {
     const int nc = n - bb;
     if (nc > 0) {
-      TrailPlan p = trail_plan(m, nc);
+      // the widest strip (fewest column tiles) gives the most row splits
+      TrailPlan p = trail_plan(m, nc, kTrailMaxStrip);
       best = std::max(best, (size_t)p.nsplit * nc * bb);
     }
   }
@@ -120,7 +121,7 @@ size_t wpart_doubles(int m, int n, int k, int b) {
     const int bbn = std::min(b, k - i - bb);
     const int nc = n - (i + bb + bbn);
     if (nc > 0) {
-      TrailPlan p = trail_plan(m - i, nc);
+      TrailPlan p = trail_plan(m - i, nc, kTrailMaxStrip);
       best = std::max(best, (size_t)p.nsplit * nc * bbn);
     }
     i += bb;
@@ -287,7 +288,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   }
   if (n - bb > 0) {
     PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(0, 0, bb, n - bb), 8.0 * m * (double)(n - bb));
-    TrailPlan pl = trail_plan(m, n - bb);
+    TrailPlan pl = trail_plan(m, n - bb, trail_strip<T>(bb));
     rc = launch_trail<T>(s, m, A, lda, 0, 0, bb, (const double*)nullptr, 0, 0, bb, n, wpart,
                          pl.nsplit, &nsp);
     if (rc) return rc;
@@ -325,7 +326,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       if (nrest > 0) {
         PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, bbn, nrest),
                       16.0 * (m - i) * (double)nrest);
-        TrailPlan pl = trail_plan(m - i, nrest);
+        TrailPlan pl = trail_plan(m - i, nrest, trail_strip<T>(std::max(bb, bbn)));
         rc = launch_trail<T>(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw, c0 + bbn,
                               c0 + bbn, n, wpart, pl.nsplit, &nsp);
         if (rc) return rc;

@@ -101,7 +101,11 @@ struct TrailPlan {
   int nsplit;
   int ntiles;
 };
-TrailPlan trail_plan(int m_rows, int ncols);
+// strip: columns per workgroup of the launch (trail_strip<T>(block width)).
+TrailPlan trail_plan(int m_rows, int ncols, int strip);
+template <typename T>
+int trail_strip(int bbm);
+constexpr int kTrailMaxStrip = 128;  // widest strip any launch uses
 // T = double: FP64 MFMA; T = float: FP32 MFMA (W' is rounded to FP32).
 template <typename T>
 int launch_trail(hipStream_t s, int m, T* a, long long lda, int i, int bbu, int bbn,

@@ -9,75 +9,14 @@
 // obtained from W' directly (V11 = unit lower top block of V), so the sample
 // update does not wait for the trailing pass.
 //
-// One workgroup per 64 columns.  The generic form (blocks wider than 64): lane
-// = column, the four waves split the rows of every triangular product, the
-// triangular solve runs in wave 0.
+// Two forms: blocks up to 64 wide (one workgroup per 64 columns) and blocks
+// 65..128 wide (2 x 2 quadrants, one workgroup per 32 columns).
 #include "internal.h"
 
 namespace rq {
 namespace {
 
 constexpr int BT = 256;
-
-template <typename T>
-__global__ __launch_bounds__(BT) void k_bupdate(int m, const T* __restrict__ a, long long lda,
-                                                int i, int bb, const double* __restrict__ tm,
-                                                const T* __restrict__ wpart, int nsplit,
-                                                double* __restrict__ wp, long long ldw,
-                                                double* __restrict__ bsk, long long ldb, int c0,
-                                                int ncols, const int* __restrict__ info) {
-  __shared__ double v0[MAX_B * 64];
-  __shared__ double v1[MAX_B * 64];
-  const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
-  const int cl = blockIdx.x * 64 + lane;  // column index relative to c0
-  const bool ok = cl < ncols;
-  const int col = c0 + cl;
-
-  // W(:, c) = sum of the split partials
-  for (int q = part; q < bb; q += 4) {
-    double s = 0.0;
-    if (ok)
-      for (int sp = 0; sp < nsplit; ++sp) s += (double)wpart[((long long)sp * ncols + cl) * bb + q];
-    v0[q * 64 + lane] = s;
-  }
-  __syncthreads();
-  // W' = T^T W   (T upper triangular, column-major bb x bb)
-  for (int r = part; r < bb; r += 4) {
-    double s = 0.0;
-    for (int q = 0; q <= r; ++q) s += tm[r * bb + q] * v0[q * 64 + lane];
-    v1[r * 64 + lane] = s;
-    if (ok) wp[(long long)cl * ldw + r] = s;
-  }
-  __syncthreads();
-  // no sketch (frozen pivots), or no more sketch updates after a zero pivot
-  if (bsk == nullptr || *info != 0) return;
-  // R12 = A(i:i+bb, col) - V11 W'
-  for (int r = part; r < bb; r += 4) {
-    double s = ok ? (double)a[(long long)col * lda + i + r] - v1[r * 64 + lane] : 0.0;
-    for (int q = 0; q < r; ++q) s -= (double)a[(long long)(i + q) * lda + i + r] * v1[q * 64 + lane];
-    v0[r * 64 + lane] = s;
-  }
-  __syncthreads();
-  // X = R11^{-1} R12 (back substitution), into v1
-  if (part == 0) {
-    for (int r = bb - 1; r >= 0; --r) {
-      double s = v0[r * 64 + lane];
-      for (int q = r + 1; q < bb; ++q)
-        s -= (double)a[(long long)(i + q) * lda + i + r] * v1[q * 64 + lane];
-      v1[r * 64 + lane] = s / (double)a[(long long)(i + r) * lda + i + r];
-    }
-  }
-  __syncthreads();
-  // B(0:bb, col) -= Rhat11 X
-  if (ok) {
-    for (int r = part; r < bb; r += 4) {
-      double s = 0.0;
-      for (int q = r; q < bb; ++q) s += bsk[(long long)(i + q) * ldb + r] * v1[q * 64 + lane];
-      bsk[(long long)col * ldb + r] -= s;
-    }
-  }
-}
-
 
 // Staged form for block widths up to 64 (the default): every global access is
 // coalesced (column-major tiles move through LDS with a padded row pitch); the
@@ -204,6 +143,214 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* __restrict__ a
   (void)m;
 }
 
+
+// Quadrant form for block widths 65..128: the bb x bb blocks (T, V11, R11,
+// Rhat11) are split into 64 x 64 quadrants staged in LDS one or two at a
+// time, so every product is a sum of 64 x 64 x 32 MFMA products and the
+// triangular solve runs as two 64-row solves in registers joined by one
+// product:  X1 = R11[1,1]^-1 R12[1],  X0 = R11[0,0]^-1 (R12[0] - R11[0,1] X1).
+// 32 columns per workgroup keep the two quadrants and the two column tiles
+// within one CU's LDS.
+constexpr int QB = 64;         // quadrant size
+constexpr int QW = 32;         // columns per workgroup
+constexpr int QP = QW + 1;     // LDS row pitch of the column tiles
+constexpr int QAP = QB + 1;    // LDS pitch of a quadrant
+
+template <typename T>
+__global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* __restrict__ a, long long lda,
+                                                  int i, int bb, const double* __restrict__ tm,
+                                                  const T* __restrict__ wpart, int nsplit,
+                                                  double* __restrict__ wp, long long ldw,
+                                                  double* __restrict__ bsk, long long ldb,
+                                                  int c0, int ncols, const int* __restrict__ info) {
+  extern __shared__ double smem[];
+  double* sQ = smem;                 // quadrant: element (row r, column k) at sQ[k * QAP + r]
+  double* sQ2 = sQ + QB * QAP;       // second quadrant, same layout
+  double* sW = sQ2 + QB * QAP;       // [q][col], 128 rows: W, then R12, then the B delta
+  double* sX = sW + 2 * QB * QP;     // [q][col], 128 rows: W', then X
+  double* sInv = sX + 2 * QB * QP;   // 1 / R11(r, r), 128 entries
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lg = lane >> 4;
+  const int cb = blockIdx.x * QW;                 // first column (relative to c0)
+  const int nc = min(QW, ncols - cb);             // columns of this workgroup
+
+  // Stage quadrant (gr, gc) of a bb x bb matrix: element (r, k) is
+  // get(64 gr + r, 64 gc + k), zero outside the block width.
+  auto stage = [&](double* dst, int gr, int gc, auto get) {
+    for (int e = tid; e < QB * QB; e += BT) {
+      const int k = e / QB, r = e % QB;
+      const int gi = QB * gr + r, gj = QB * gc + k;
+      dst[k * QAP + r] = (gi < bb && gj < bb) ? get(gi, gj) : 0.0;
+    }
+  };
+  // acc += L(16 wave + row, :) x rm(0:64, 0:32) for a quadrant L in LDS;
+  // acc[t][e] = C(16 wave + acc_row(lg, e), 16 t + l16); `keep(r, k)` masks L.
+  auto mmq = [&](const double* q, auto keep, const double* rm, v4d (&acc)[2]) {
+#pragma unroll 4
+    for (int kk = 0; kk < QB / 4; ++kk) {
+      const int k = 4 * kk + lg, r = 16 * wave + l16;
+      const double av = keep(r, k) ? q[k * QAP + r] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[t] = mfma_f64(av, rm[k * QP + 16 * t + l16], acc[t]);
+    }
+  };
+  auto all = [](int, int) { return true; };
+  auto zero = [](v4d (&acc)[2]) {
+    acc[0] = v4d{0.0, 0.0, 0.0, 0.0};
+    acc[1] = v4d{0.0, 0.0, 0.0, 0.0};
+  };
+  auto tget = [&](int r, int k) { return tm[r * bb + k]; };  // T^T(r, k) = T(k, r)
+
+  // W(:, cb + c) = sum of the split partials
+  for (int e = tid; e < 2 * QB * QW; e += BT) {
+    const int c = e / (2 * QB), q = e % (2 * QB);
+    double s = 0.0;
+    if (c < nc && q < bb)
+      for (int sp = 0; sp < nsplit; ++sp)
+        s += (double)wpart[((long long)sp * ncols + cb + c) * bb + q];
+    sW[q * QP + c] = s;
+  }
+  // W' = T^T W (T^T lower triangular): W'[0] = T00^T W[0],
+  // W'[1] = T01^T W[0] + T11^T W[1]
+  stage(sQ, 0, 0, tget);
+  __syncthreads();
+  v4d acc[2];
+  zero(acc);
+  mmq(sQ, [](int r, int k) { return k <= r; }, sW, acc);
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sX[(16 * wave + acc_row<double>(lg, e)) * QP + 16 * t + l16] = acc[t][e];
+  stage(sQ, 1, 0, tget);
+  stage(sQ2, 1, 1, tget);
+  __syncthreads();
+  zero(acc);
+  mmq(sQ, all, sW, acc);
+  mmq(sQ2, [](int r, int k) { return k <= r; }, sW + QB * QP, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      sX[(QB + 16 * wave + acc_row<double>(lg, e)) * QP + 16 * t + l16] = acc[t][e];
+  __syncthreads();
+  for (int e = tid; e < nc * bb; e += BT) {
+    const int c = e / bb, r = e % bb;
+    wp[(long long)(cb + c) * ldw + r] = sX[r * QP + c];
+  }
+  if (bsk == nullptr || *info != 0) return;
+
+  // R12 = A(i:i+bb, col) - V11 W'  (V11 unit lower: A(i + r, i + q), q < r)
+  auto aget = [&](int r, int k) { return (double)a[(long long)(i + k) * lda + i + r]; };
+  for (int e = tid; e < 2 * QB * QW; e += BT) {
+    const int c = e / (2 * QB), r = e % (2 * QB);
+    sW[r * QP + c] = (c < nc && r < bb) ? (double)a[(long long)(c0 + cb + c) * lda + i + r] : 0.0;
+  }
+  if (tid < 2 * QB) sInv[tid] = (tid < bb) ? 1.0 / aget(tid, tid) : 1.0;
+  stage(sQ, 0, 0, aget);
+  __syncthreads();
+  // rows 0..63: V00 W'[0]
+  zero(acc);
+  mmq(sQ, [](int r, int k) { return k < r; }, sX, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * wave + acc_row<double>(lg, e), c = 16 * t + l16;
+      sW[r * QP + c] = sW[r * QP + c] - sX[r * QP + c] - acc[t][e];
+    }
+  __syncthreads();
+  // rows 64..127: V10 W'[0] + V11 W'[1]
+  stage(sQ, 1, 0, aget);
+  stage(sQ2, 1, 1, aget);
+  __syncthreads();
+  zero(acc);
+  mmq(sQ, all, sX, acc);
+  mmq(sQ2, [](int r, int k) { return k < r; }, sX + QB * QP, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = QB + 16 * wave + acc_row<double>(lg, e), c = 16 * t + l16;
+      sW[r * QP + c] = sW[r * QP + c] - sX[r * QP + c] - acc[t][e];
+    }
+  __syncthreads();
+
+  // 64-row back substitution of the rows h*64.. against the quadrant in sQ
+  // (R11(64h + q, 64h + r) at sQ[r * QAP + q]), column `lane` in registers.
+  auto solve = [&](int h) {
+    if (wave == 0 && lane < QW) {
+      const int nb = min(QB, bb - QB * h);
+      double y[QB];
+#pragma unroll
+      for (int r = 0; r < QB; ++r) y[r] = sW[(QB * h + r) * QP + lane];
+#pragma unroll
+      for (int r = QB - 1; r >= 0; --r) {
+        if (r < nb) {
+          const double x = y[r] * sInv[QB * h + r];
+          y[r] = x;
+#pragma unroll
+          for (int q = 0; q < r; ++q) y[q] -= sQ[r * QAP + q] * x;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < QB; ++r) sX[(QB * h + r) * QP + lane] = (r < nb) ? y[r] : 0.0;
+    }
+  };
+  // X1 = R11[1,1]^-1 R12[1]
+  stage(sQ, 1, 1, aget);
+  stage(sQ2, 0, 1, aget);  // R11[0,1] for the join
+  __syncthreads();
+  solve(1);
+  __syncthreads();
+  // R12[0] -= R11[0,1] X1
+  zero(acc);
+  mmq(sQ2, all, sX + QB * QP, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * wave + acc_row<double>(lg, e), c = 16 * t + l16;
+      sW[r * QP + c] -= acc[t][e];
+    }
+  __syncthreads();
+  // X0 = R11[0,0]^-1 R12[0]
+  stage(sQ, 0, 0, aget);
+  __syncthreads();
+  solve(0);
+  __syncthreads();
+
+  // delta = Rhat11 X (Rhat11 = triu(B(0:bb, i:i+bb))): rows 0..63 take
+  // quadrants (0,0) and (0,1), rows 64..127 quadrant (1,1)
+  auto bget = [&](int r, int k) { return bsk[(long long)(i + k) * ldb + r]; };
+  stage(sQ, 0, 0, bget);
+  stage(sQ2, 0, 1, bget);
+  __syncthreads();
+  zero(acc);
+  mmq(sQ, [](int r, int k) { return k >= r; }, sX, acc);
+  mmq(sQ2, all, sX + QB * QP, acc);
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sW[(16 * wave + acc_row<double>(lg, e)) * QP + 16 * t + l16] = acc[t][e];
+  stage(sQ, 1, 1, bget);
+  __syncthreads();
+  zero(acc);
+  mmq(sQ, [](int r, int k) { return k >= r; }, sX + QB * QP, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      sW[(QB + 16 * wave + acc_row<double>(lg, e)) * QP + 16 * t + l16] = acc[t][e];
+  __syncthreads();
+  for (int e = tid; e < nc * bb; e += BT) {
+    const int c = e / bb, r = e % bb;
+    bsk[(long long)(c0 + cb + c) * ldb + r] -= sW[r * QP + c];
+  }
+  (void)m;
+}
+
 }  // namespace
 
 template <typename T>
@@ -221,8 +368,12 @@ int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int b
     RQ_HIP_CHECK(hipGetLastError());
     return RQ_OK;
   }
-  hipLaunchKernelGGL(k_bupdate<T>, dim3((ncols + 63) / 64), dim3(BT), 0, s, m, a, lda, i, bb, t,
-                     wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info);
+  static_assert(2 * QB >= MAX_B, "the quadrant form covers every block width");
+  const size_t shmem = (2 * (size_t)QB * QAP + 4 * (size_t)QB * QP + 2 * QB) * sizeof(double);
+  RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bupdate_q<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  hipLaunchKernelGGL(k_bupdate_q<T>, dim3((ncols + QW - 1) / QW), dim3(BT), shmem, s, m, a, lda, i,
+                     bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }

@@ -18,15 +18,16 @@
 // chunk e is taken as the rows {acc_row(g, e) : g = 0..3}, so no data moves
 // between the two products.
 //
-// Grid: x = 64-column strips (one 16-column slab per wave), y = row splits;
-// each workgroup walks its rows in 64-row tiles and keeps its W_{i+1} slab in
-// registers; row splits write separate partial sums.
+// Grid: x = column strips (NW waves of 16 columns each), y = row splits;
+// each workgroup walks its rows in 32-row tiles and keeps its W_{i+1} slab in
+// registers; row splits write separate partial sums.  Every wave of a
+// workgroup reads the reflector rows the workgroup staged in LDS, so wider
+// strips stage less per unit of work; the register budget decides how wide.
 #include "internal.h"
 
 namespace rq {
 namespace {
 
-constexpr int TT = 256;
 constexpr int TR = 32;  // rows per tile
 
 // LDS layouts (no padding; the XOR swizzles make both the row-contiguous
@@ -50,13 +51,16 @@ struct TrailMfma<float> {
   static RQ_DEV acc_t run(float a, float b, acc_t c) { return mfma_f32(a, b, c); }
 };
 
-template <typename T, int BBM>
-__global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail(
+// NW waves per workgroup, compiled for WPS waves per SIMD (512 / WPS
+// registers per lane).
+template <typename T, int BBM, int NW, int WPS>
+__global__ __launch_bounds__(64 * NW, WPS) void k_trail(
     int m, T* __restrict__ a, long long lda, int i, int bbu, int bbn,
     const double* __restrict__ wp, long long ldw, int w0, int c_begin, int c_end,
     T* __restrict__ wpart, int rows_per_split) {
   static_assert(BBM % 32 == 0, "block width must be a multiple of 32");
   typedef typename TrailMfma<T>::acc_t acc_t;
+  constexpr int TT = 64 * NW;
   constexpr int QS = TT / TR;       // reflector columns staged per pass of the block
   constexpr int NQ = BBM / QS;      // reflector values staged per thread and matrix
   __shared__ T sVuT[BBM * TR];
@@ -64,7 +68,7 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail(
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr16 = lane & 15, lg = lane >> 4;
-  const int col = c_begin + blockIdx.x * 64 + wave * 16 + lr16;
+  const int col = c_begin + blockIdx.x * (16 * NW) + wave * 16 + lr16;
   const bool colok = col < c_end;
   const int ri0 = i + blockIdx.y * rows_per_split;
   const int ri1 = min(m, ri0 + rows_per_split);
@@ -149,11 +153,11 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail(
     }
     __syncthreads();
     // ---- fetch the next tile while this one is on the MFMAs ----
-    const bool more = r0 + TR < ri1;
-    if (more) {
-      fetch_v(r0 + TR);
-      fetch_a(r0 + TR, dn);
-    }
+    // Unconditional: after the last tile the clamped addresses stay valid and
+    // the values go unused.  (Under a branch, the wait analysis at the join
+    // made the MFMAs below wait for these loads.)
+    fetch_v(r0 + TR);
+    fetch_a(r0 + TR, dn);
 
     if (bbu > 0) {
 #pragma unroll
@@ -188,10 +192,8 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail(
         }
     }
     __syncthreads();
-    if (more) {
 #pragma unroll
-      for (int b = 0; b < TR / 16; ++b) d[b] = dn[b];
-    }
+    for (int b = 0; b < TR / 16; ++b) d[b] = dn[b];
   }
 
   if (bbn > 0 && colok) {
@@ -208,15 +210,32 @@ __global__ __launch_bounds__(TT, BBM <= 64 ? 2 : 1) void k_trail(
 
 }  // namespace
 
-TrailPlan trail_plan(int m_rows, int ncols) {
+TrailPlan trail_plan(int m_rows, int ncols, int strip) {
   TrailPlan p;
-  p.ntiles = (ncols + 63) / 64;
+  p.ntiles = (ncols + strip - 1) / strip;
   int ns = 1;
   // aim for at least two workgroups per compute unit; keep >= 256 rows per split
   while (p.ntiles * ns < 512 && (m_rows / (ns * 2)) >= 256) ns *= 2;
   p.nsplit = ns;
   return p;
 }
+
+// Launch shape: four waves per workgroup at two waves per SIMD for blocks up
+// to 64 wide; for wider blocks the FP64 form needs a whole SIMD per wave
+// (472 registers), while the FP32 form fits eight-wave workgroups at two
+// waves per SIMD (246 registers), which halves its reflector staging.
+template <typename T>
+static int trail_waves(int bbm) {
+  return (bbm > 64 && sizeof(T) == 4) ? 8 : 4;
+}
+
+template <typename T>
+int trail_strip(int bbm) {
+  return 16 * trail_waves<T>(bbm);
+}
+static_assert(16 * 8 <= kTrailMaxStrip, "workspace sizing assumes the widest strip");
+template int trail_strip<double>(int);
+template int trail_strip<float>(int);
 
 template <typename T>
 int launch_trail(hipStream_t s, int m, T* a, long long lda, int i, int bbu, int bbn,
@@ -229,19 +248,22 @@ int launch_trail(hipStream_t s, int m, T* a, long long lda, int i, int bbu, int 
   int rps = (rows + nsplit - 1) / nsplit;
   rps = (rps + TR - 1) / TR * TR;
   const int nsp = (rows + rps - 1) / rps;
-  dim3 grid((ncols + 63) / 64, nsp);
   const int bbm = bbu > bbn ? bbu : bbn;
+  if (bbm > 128) return RQ_ERR_LIMIT;
+  const int nw = trail_waves<T>(bbm), strip = 16 * nw;
+  const dim3 grid((ncols + strip - 1) / strip, nsp), block(64 * nw);
   if (bbm <= 32)
-    hipLaunchKernelGGL((k_trail<T, 32>), grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw, w0,
-                       c_begin, c_end, wpart, rps);
-  else if (bbm <= 64)
-    hipLaunchKernelGGL((k_trail<T, 64>), grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw, w0,
-                       c_begin, c_end, wpart, rps);
-  else if (bbm <= 128)
-    hipLaunchKernelGGL((k_trail<T, 128>), grid, dim3(TT), 0, s, m, a, lda, i, bbu, bbn, wp, ldw,
+    hipLaunchKernelGGL((k_trail<T, 32, 4, 2>), grid, block, 0, s, m, a, lda, i, bbu, bbn, wp, ldw,
                        w0, c_begin, c_end, wpart, rps);
+  else if (bbm <= 64)
+    hipLaunchKernelGGL((k_trail<T, 64, 4, 2>), grid, block, 0, s, m, a, lda, i, bbu, bbn, wp, ldw,
+                       w0, c_begin, c_end, wpart, rps);
+  else if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL((k_trail<T, 128, 8, 2>), grid, block, 0, s, m, a, lda, i, bbu, bbn, wp,
+                       ldw, w0, c_begin, c_end, wpart, rps);
   else
-    return RQ_ERR_LIMIT;
+    hipLaunchKernelGGL((k_trail<T, 128, 4, 1>), grid, block, 0, s, m, a, lda, i, bbu, bbn, wp,
+                       ldw, w0, c_begin, c_end, wpart, rps);
   RQ_HIP_CHECK(hipGetLastError());
   *nsp_out = nsp;  // number of partial sums written
   return RQ_OK;

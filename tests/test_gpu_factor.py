@@ -106,6 +106,8 @@ def test_sketch_with_user_omega(rq):
     (500, 400, 160, 80, 16),   # tall sketch (l = 96): four columns per thread, several workgroups
     (400, 300, 150, 128, 8),   # a 128-wide panel in two halves, then a narrow one after it
     (600, 500, 256, 128, 16),  # 128-wide panels after 128-wide blocks
+    (256, 16384, 192, 64, 8),  # sketch QRCP over the full-width grid: 64 workgroups exchange candidates
+    (160, 32768, 128, 64, 8),  # 128 workgroups; candidate headers read first, then the winner's column
 ])
 def test_factor_parity(rq, m, n, k, b, p):
     a = separated_lowrank(m, n, 11)

@@ -36,35 +36,42 @@ constexpr int CT = 256;
 
 // ---- pending update A(rp:m, i+coff : i+coff+bb) -= V_prev W'(:, coff : coff+bb)
 // (V_prev unit lower at column rp = i - bbp) ----
+// One row per lane (coalesced column accesses): each thread holds its row of
+// V_prev in registers and updates a quarter of the bb columns; W' is staged
+// in LDS and read by wave-uniform (broadcast) loads.  Each entry is
+// a - sum_q V(r, q) W'(q, c), the sum taken over q = 0, 1, ... in order.
+constexpr int PR = 64;  // rows per workgroup of the pending update
 template <typename T>
 __global__ __launch_bounds__(CT) void k_cq_pend(int m, T* __restrict__ a, long long lda, int i,
                                                 int coff, int bb, int bbp,
                                                 const double* __restrict__ wp, long long ldw) {
-  __shared__ double sv[CR * CP];   // V_prev rows of this workgroup, [row][q]
-  __shared__ double sw[CB * CP];   // W'(q, c) at sw[c * CP + q]
+  __shared__ double sw[CB * CB];  // W'(q, c) at sw[c * CB + q], zero for q >= bbp
   const int rp = i - bbp;
-  const int r0 = rp + blockIdx.x * CR;
   const int tid = threadIdx.x;
-  for (int e = tid; e < CR * bbp; e += CT) {
-    const int q = e / CR, rr = e % CR;
-    const int r = r0 + rr, d = r - rp;
-    double v = 0.0;
-    if (r < m) v = (d > q) ? (double)a[(long long)(rp + q) * lda + r] : (d == q ? 1.0 : 0.0);
-    sv[rr * CP + q] = v;
+  const int rr = tid % PR;
+  const int part = __builtin_amdgcn_readfirstlane(tid / PR);  // one part per wave
+  const int r = rp + blockIdx.x * PR + rr;
+  for (int e = tid; e < bb * CB; e += CT) {
+    const int c = e / CB, q = e % CB;
+    sw[e] = q < bbp ? wp[(long long)(coff + c) * ldw + q] : 0.0;
   }
-  for (int e = tid; e < bb * bbp; e += CT) {
-    const int c = e / bbp, q = e % bbp;
-    sw[c * CP + q] = wp[(long long)(coff + c) * ldw + q];
+  // this thread's row of V_prev (loads from clamped addresses, masked after)
+  const int rs = r < m ? r : m - 1;
+  const int d = r - rp;
+  double v[CB];
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    const double x = (double)a[(long long)(rp + (q < bbp ? q : 0)) * lda + rs];
+    v[q] = (q < bbp && d > q) ? x : ((q < bbp && d == q) ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int c = tid % CB, rg = tid / CB;
-  if (c >= bb) return;
-  T* col = a + (long long)(i + coff + c) * lda;
-  for (int rr = rg; rr < CR; rr += CT / CB) {
-    const int r = r0 + rr;
-    if (r >= m) break;
+  if (r >= m) return;
+  for (int c = part; c < bb; c += CT / PR) {
+    const double* w = sw + c * CB;
     double s = 0.0;
-    for (int q = 0; q < bbp; ++q) s += sv[rr * CP + q] * sw[c * CP + q];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) s += v[q] * w[q];
+    T* col = a + (long long)(i + coff + c) * lda;
     col[r] = (T)((double)col[r] - s);
   }
 }
@@ -769,7 +776,7 @@ int launch_panel_cq(hipStream_t s, int m, T* a, long long lda, int i, int bb, in
   T* x = a + (long long)i * lda + i;
   if (bbp > 0) {
     const int prow = m - (i - bbp);
-    hipLaunchKernelGGL(k_cq_pend<T>, dim3((prow + CR - 1) / CR), dim3(CT), 0, s, m, a, lda, i, 0,
+    hipLaunchKernelGGL(k_cq_pend<T>, dim3((prow + PR - 1) / PR), dim3(CT), 0, s, m, a, lda, i, 0,
                        bb, bbp, wp, ldw);
   }
   hipLaunchKernelGGL(k_cq_gram<T>, dim3(nchunk), dim3(CT), 0, s, rows, (const T*)x, lda, bb, part,
@@ -800,7 +807,7 @@ int launch_cq_pend(hipStream_t s, int m, T* a, long long lda, int i, int coff, i
                    const double* wp, long long ldw) {
   if (nc < 1 || nc > CB || bbp < 1 || bbp > CB) return RQ_ERR_LIMIT;
   const int prow = m - (i - bbp);
-  hipLaunchKernelGGL(k_cq_pend<T>, dim3((prow + CR - 1) / CR), dim3(CT), 0, s, m, a, lda, i, coff,
+  hipLaunchKernelGGL(k_cq_pend<T>, dim3((prow + PR - 1) / PR), dim3(CT), 0, s, m, a, lda, i, coff,
                      nc, bbp, wp, ldw);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;

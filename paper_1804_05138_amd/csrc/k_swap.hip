@@ -13,23 +13,45 @@ namespace {
 constexpr int ST = 256;
 constexpr int SLAB = 32;  // rows per workgroup
 
-template <typename T>
-__global__ __launch_bounds__(ST) void k_apply_pairs(int rows, T* __restrict__ a, long long lda,
-                                                    int c0, const int* __restrict__ pairs,
-                                                    const int* __restrict__ npairs) {
-  __shared__ T buf[2 * MAX_B * SLAB];
-  const int np = *npairs;
-  const int r0 = blockIdx.x * SLAB;
-  const int nrow = min(SLAB, rows - r0);
-  if (nrow <= 0 || np <= 0) return;
+// Moves the listed columns of rows [r0, r0 + nrow) of x (leading dimension
+// ldx, column offset c0): every source first into LDS, then every destination.
+template <typename S>
+RQ_DEV void move_slab(S* __restrict__ x, long long ldx, int c0, int r0, int nrow,
+                      const int* __restrict__ pairs, int np, S* buf) {
   for (int e = threadIdx.x; e < np * SLAB; e += ST) {
     const int p = e / SLAB, r = e % SLAB;
-    if (r < nrow) buf[e] = a[(long long)(c0 + pairs[2 * p + 1]) * lda + r0 + r];
+    if (r < nrow) buf[e] = x[(long long)(c0 + pairs[2 * p + 1]) * ldx + r0 + r];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < np * SLAB; e += ST) {
     const int p = e / SLAB, r = e % SLAB;
-    if (r < nrow) a[(long long)(c0 + pairs[2 * p]) * lda + r0 + r] = buf[e];
+    if (r < nrow) x[(long long)(c0 + pairs[2 * p]) * ldx + r0 + r] = buf[e];
+  }
+}
+
+// One launch for the three moves of a block: the first na workgroups take
+// SLAB-row slabs of A, the next nw slabs of the pending W' block (wrows rows,
+// no column offset), and the last one (when jpvt is given) the permutation
+// vector.  Each workgroup touches only its own rows, so the roles never race.
+template <typename T>
+__global__ __launch_bounds__(ST) void k_apply_pairs(int rows, T* __restrict__ a, long long lda,
+                                                    int c0, int na, double* __restrict__ wp,
+                                                    int wrows, long long ldw, int nw,
+                                                    int* __restrict__ jpvt,
+                                                    const int* __restrict__ pairs,
+                                                    const int* __restrict__ npairs) {
+  __shared__ double buf[2 * MAX_B * SLAB];
+  const int np = *npairs;
+  if (np <= 0) return;
+  const int g = blockIdx.x;
+  if (g < na) {
+    const int r0 = g * SLAB;
+    move_slab<T>(a, lda, c0, r0, min(SLAB, rows - r0), pairs, np, reinterpret_cast<T*>(buf));
+  } else if (g < na + nw) {
+    const int r0 = (g - na) * SLAB;
+    move_slab<double>(wp, ldw, 0, r0, min(SLAB, wrows - r0), pairs, np, buf);
+  } else if (jpvt != nullptr) {
+    move_slab<int>(jpvt, 1LL, c0, 0, 1, pairs, np, reinterpret_cast<int*>(buf));
   }
 }
 
@@ -40,15 +62,12 @@ int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* j
                        int wrows, long long ldw, int w0, const int* pairs, const int* npairs,
                        int max_pairs) {
   if (max_pairs > 2 * MAX_B) return RQ_ERR_LIMIT;
-  if (m > 0)
-    hipLaunchKernelGGL(k_apply_pairs<T>, dim3((m + SLAB - 1) / SLAB), dim3(ST), 0, s, m, a,
-                       lda, c0, pairs, npairs);
-  if (wp != nullptr && wrows > 0)
-    hipLaunchKernelGGL(k_apply_pairs<double>, dim3((wrows + SLAB - 1) / SLAB), dim3(ST), 0, s,
-                       wrows, wp, ldw, 0, pairs, npairs);
-  if (jpvt != nullptr)
-    hipLaunchKernelGGL(k_apply_pairs<int>, dim3(1), dim3(ST), 0, s, 1, jpvt, 1LL, c0, pairs,
-                       npairs);
+  const int na = m > 0 ? (m + SLAB - 1) / SLAB : 0;
+  const int nw = (wp != nullptr && wrows > 0) ? (wrows + SLAB - 1) / SLAB : 0;
+  const int nj = jpvt != nullptr ? 1 : 0;
+  if (na + nw + nj > 0)
+    hipLaunchKernelGGL(k_apply_pairs<T>, dim3(na + nw + nj), dim3(ST), 0, s, m, a, lda, c0, na, wp,
+                       wrows, ldw, nw, jpvt, pairs, npairs);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }

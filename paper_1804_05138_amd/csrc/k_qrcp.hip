@@ -56,7 +56,7 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
   __shared__ double s_wn[NW];
   __shared__ int s_wp[NW];
   __shared__ int s_ws[NW];
-  // the G candidate headers, then the winner's column
+  // the winner's column of the step
   extern __shared__ double s_rec[];
 
   // A zero sketch pivot in an earlier block: no more pivoting (identity).
@@ -133,17 +133,16 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
                  2LL * cs, G, seq, bar);
 
     // ---- (3) global winner and its reflector, computed by every workgroup ----
-    // headers first (each wave scans them and reduces with DPP), then the
-    // winner's column (rows 0..l-1)
+    // every wave reads the headers itself (lane q: records q, q + 64, ...)
+    // and reduces with DPP; then the winner's column (rows 0..l-1) into LDS
     const double* recs = cand + (long long)(t & 1) * G * cs;
-    for (int e = tid; e < G * 4; e += QT) s_rec[e] = recs[(e >> 2) * cs + (e & 3)];
-    __syncthreads();
     double gn = -2.0;
     int jpos = INT_MAX;
     int ww = 0;
     for (int q = lane; q < G; q += 64) {
-      const double n = s_rec[q * 4];
-      const int p = (n >= 0.0) ? (int)s_rec[q * 4 + 1] : INT_MAX;
+      const double n = recs[(long long)q * cs];
+      const double pd = recs[(long long)q * cs + 1];
+      const int p = (n >= 0.0) ? (int)pd : INT_MAX;
       if (argbetter(n, p, gn, jpos)) {
         gn = n;
         jpos = p;
@@ -151,8 +150,8 @@ __global__ __launch_bounds__(QT, 1) void k_qrcp_sketch(
       }
     }
     wave_argmax(gn, jpos, ww);
-    int wslot = (int)s_rec[ww * 4 + 2];
-    double* wcol = s_rec + G * 4;
+    int wslot = (int)recs[(long long)ww * cs + 2];
+    double* wcol = s_rec;
     for (int r = tid; r < l; r += QT) wcol[r] = recs[(long long)ww * cs + 4 + r];
     __syncthreads();
     // A winner that is not a column of this block (no candidate norm is a
@@ -252,10 +251,10 @@ int launch_t(hipStream_t s, double* b, long long ldb, int l, int nc, int nsteps,
   int dev = 0, ncu = 0, per_cu = 0;
   RQ_HIP_CHECK(hipGetDevice(&dev));
   RQ_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  // LDS: the G headers, then the winner's column.  (Reading every record,
-  // columns included, in one round trip measured 11% slower than two short
-  // round trips at every width from 4 to 128 workgroups.)
-  const size_t shmem = ((size_t)G * 4 + cs) * sizeof(double);
+  // LDS: the winner's column.  (Reading every record, columns included, in
+  // one round trip measured 11% slower than two short round trips, headers
+  // then the winner's column, at every width from 4 to 128 workgroups.)
+  const size_t shmem = (size_t)cs * sizeof(double);
   RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   RQ_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(

@@ -220,14 +220,21 @@ RQ_DEV void wait_all_seq(const unsigned* seq0, long long stride, int n, unsigned
     const int lane = threadIdx.x & 63;
     for (int q = lane; q < n; q += 64) {
       const unsigned* w = seq0 + (long long)q * stride;
+      // two polls in flight: each check waits only for the older one
       unsigned spins = 0;
-      while (atomic_peek_agent(w) != seq) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > RQ_SPIN_LIMIT) {
+      unsigned va = atomic_peek_agent(w);
+      unsigned vb = atomic_peek_agent(w);
+      for (;;) {
+        if (va == seq) break;
+        va = atomic_peek_agent(w);
+        if (vb == seq) break;
+        vb = atomic_peek_agent(w);
+        spins += 2;
+        if (spins > RQ_SPIN_LIMIT) {
           atomicOr(&bar->err, 1u);
           break;
         }
-        if ((spins & 1023u) == 0 && atomic_peek_agent(&bar->err)) break;
+        if ((spins & 1022u) == 0 && atomic_peek_agent(&bar->err)) break;
       }
     }
     // one acquire for the workgroup (the invalidation is per cache, not per wave)

@@ -61,20 +61,60 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* __restrict__ a
     }
   };
 
-  for (int e = tid; e < SB * SB; e += BT) {
-    const int r = e / SB, q = e % SB;
+  // Every global read of the kernel is issued up front from clamped (always
+  // valid) addresses and masked afterwards, so the reads cost one memory round
+  // trip per split of W instead of one per element.
+  constexpr int NE = SB * SB / BT;   // elements of a bb x bb block per thread
+  constexpr int NC = SB * CW / BT;   // elements of a bb x CW column tile per thread
+  static_assert(NE * BT == SB * SB && NC * BT == SB * CW, "tiles split evenly over the threads");
+  const bool upd = bsk != nullptr;   // uniform: the sample update runs (not frozen pivots)
+  double tv[NE], av[NE], rv[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * BT, r = e / SB, q = e % SB;   // column r, row q
     const bool in = r < bb && q < bb;
-    sT[r * AP + q] = in ? tm[r * bb + q] : 0.0;
-    sA[r * AP + q] = in ? (double)a[(long long)(i + r) * lda + i + q] : 0.0;  // column r, row q
+    const int rs = in ? r : 0, qs = in ? q : 0;
+    tv[u] = tm[rs * bb + qs];
+    av[u] = (double)a[(long long)(i + rs) * lda + i + qs];
+    rv[u] = upd ? bsk[(long long)(i + rs) * ldb + qs] : 0.0;
   }
-  // W(:, cb + c) = sum of the split partials (contiguous per column)
-  for (int e = tid; e < SB * CW; e += BT) {
-    const int c = e / SB, q = e % SB;
-    double s = 0.0;
-    if (c < nc && q < bb)
-      for (int sp = 0; sp < nsplit; ++sp)
-        s += (double)wpart[((long long)sp * ncols + cb + c) * bb + q];
-    sW[q * SP + c] = s;
+  double a12[NC], bo[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int e = tid + u * BT;
+    const int c = e / SB, r = e % SB;     // R12 start: A(i + r, c0 + cb + c)
+    const bool ok = c < nc && r < bb;
+    a12[u] = (double)a[(long long)(c0 + cb + (ok ? c : 0)) * lda + i + (ok ? r : 0)];
+    const int c2 = e / bb, r2 = e % bb;   // B(r2, c0 + cb + c2), updated at the end
+    const bool ok2 = e < nc * bb;
+    bo[u] = upd ? bsk[(long long)(c0 + cb + (ok2 ? c2 : 0)) * ldb + (ok2 ? r2 : 0)] : 0.0;
+  }
+  // W(:, cb + c) = sum of the split partials, in split order
+  double ws[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) ws[u] = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    double pv[NC];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int e = tid + u * BT, c = e / SB, q = e % SB;
+      const bool ok = c < nc && q < bb;
+      pv[u] = (double)wpart[((long long)sp * ncols + cb + (ok ? c : 0)) * bb + (ok ? q : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) ws[u] += pv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * BT, r = e / SB, q = e % SB;
+    const bool in = r < bb && q < bb;
+    sT[r * AP + q] = in ? tv[u] : 0.0;
+    sA[r * AP + q] = in ? av[u] : 0.0;  // column r, row q
+  }
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int e = tid + u * BT, c = e / SB, q = e % SB;
+    sW[q * SP + c] = (c < nc && q < bb) ? ws[u] : 0.0;
   }
   __syncthreads();
   v4d acc[4];
@@ -91,13 +131,15 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* __restrict__ a
   }
   if (bsk == nullptr || *info != 0) return;
   // Rhat11 = triu(B(0:bb, i:i+bb)) into sT; R12 starts as A(i:i+bb, col)
-  for (int e = tid; e < SB * SB; e += BT) {
-    const int r = e / SB, q = e % SB;   // column r, row q
-    sT[r * AP + q] = (q <= r && r < bb) ? bsk[(long long)(i + r) * ldb + q] : 0.0;
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * BT, r = e / SB, q = e % SB;   // column r, row q
+    sT[r * AP + q] = (q <= r && r < bb) ? rv[u] : 0.0;
   }
-  for (int e = tid; e < SB * CW; e += BT) {
-    const int c = e / SB, r = e % SB;
-    sW[r * SP + c] = (c < nc && r < bb) ? (double)a[(long long)(c0 + cb + c) * lda + i + r] : 0.0;
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int e = tid + u * BT, c = e / SB, r = e % SB;
+    sW[r * SP + c] = (c < nc && r < bb) ? a12[u] : 0.0;
   }
   if (tid < SB) sInv[tid] = (tid < bb) ? 1.0 / sA[tid * AP + tid] : 1.0;
   __syncthreads();
@@ -136,9 +178,10 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* __restrict__ a
 #pragma unroll
     for (int e = 0; e < 4; ++e) sW[(16 * wave + acc_row<double>(lg, e)) * SP + 16 * t + l16] = acc[t][e];
   __syncthreads();
-  for (int e = tid; e < nc * bb; e += BT) {
-    const int c = e / bb, r = e % bb;
-    bsk[(long long)(c0 + cb + c) * ldb + r] -= sW[r * SP + c];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int e = tid + u * BT, c = e / bb, r = e % bb;
+    if (e < nc * bb) bsk[(long long)(c0 + cb + c) * ldb + r] = bo[u] - sW[r * SP + c];
   }
   (void)m;
 }

@@ -219,11 +219,24 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* __restrict__ a
 
   // Stage quadrant (gr, gc) of a bb x bb matrix: element (r, k) is
   // get(64 gr + r, 64 gc + k), zero outside the block width.
+  // All reads of a thread are issued before any LDS store (clamped addresses,
+  // masked afterwards), so a stage costs one memory round trip.
+  constexpr int NS = QB * QB / BT;
+  static_assert(NS * BT == QB * QB, "quadrant splits evenly over the threads");
   auto stage = [&](double* dst, int gr, int gc, auto get) {
-    for (int e = tid; e < QB * QB; e += BT) {
-      const int k = e / QB, r = e % QB;
+    double v[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + u * BT, k = e / QB, r = e % QB;
       const int gi = QB * gr + r, gj = QB * gc + k;
-      dst[k * QAP + r] = (gi < bb && gj < bb) ? get(gi, gj) : 0.0;
+      const bool ok = gi < bb && gj < bb;
+      v[u] = get(ok ? gi : 0, ok ? gj : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + u * BT, k = e / QB, r = e % QB;
+      const int gi = QB * gr + r, gj = QB * gc + k;
+      dst[k * QAP + r] = (gi < bb && gj < bb) ? v[u] : 0.0;
     }
   };
   // acc += L(16 wave + row, :) x rm(0:64, 0:32) for a quadrant L in LDS;
@@ -244,14 +257,30 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* __restrict__ a
   };
   auto tget = [&](int r, int k) { return tm[r * bb + k]; };  // T^T(r, k) = T(k, r)
 
-  // W(:, cb + c) = sum of the split partials
-  for (int e = tid; e < 2 * QB * QW; e += BT) {
-    const int c = e / (2 * QB), q = e % (2 * QB);
-    double s = 0.0;
-    if (c < nc && q < bb)
-      for (int sp = 0; sp < nsplit; ++sp)
-        s += (double)wpart[((long long)sp * ncols + cb + c) * bb + q];
-    sW[q * QP + c] = s;
+  // W(:, cb + c) = sum of the split partials, in split order (every read of a
+  // split in flight together)
+  constexpr int NCQ = 2 * QB * QW / BT;
+  static_assert(NCQ * BT == 2 * QB * QW, "column tile splits evenly over the threads");
+  {
+    double ws[NCQ];
+#pragma unroll
+    for (int u = 0; u < NCQ; ++u) ws[u] = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+      double pv[NCQ];
+#pragma unroll
+      for (int u = 0; u < NCQ; ++u) {
+        const int e = tid + u * BT, c = e / (2 * QB), q = e % (2 * QB);
+        const bool ok = c < nc && q < bb;
+        pv[u] = (double)wpart[((long long)sp * ncols + cb + (ok ? c : 0)) * bb + (ok ? q : 0)];
+      }
+#pragma unroll
+      for (int u = 0; u < NCQ; ++u) ws[u] += pv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NCQ; ++u) {
+      const int e = tid + u * BT, c = e / (2 * QB), q = e % (2 * QB);
+      sW[q * QP + c] = (c < nc && q < bb) ? ws[u] : 0.0;
+    }
   }
   // W' = T^T W (T^T lower triangular): W'[0] = T00^T W[0],
   // W'[1] = T01^T W[0] + T11^T W[1]
@@ -285,9 +314,19 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* __restrict__ a
 
   // R12 = A(i:i+bb, col) - V11 W'  (V11 unit lower: A(i + r, i + q), q < r)
   auto aget = [&](int r, int k) { return (double)a[(long long)(i + k) * lda + i + r]; };
-  for (int e = tid; e < 2 * QB * QW; e += BT) {
-    const int c = e / (2 * QB), r = e % (2 * QB);
-    sW[r * QP + c] = (c < nc && r < bb) ? (double)a[(long long)(c0 + cb + c) * lda + i + r] : 0.0;
+  {
+    double v[NCQ];
+#pragma unroll
+    for (int u = 0; u < NCQ; ++u) {
+      const int e = tid + u * BT, c = e / (2 * QB), r = e % (2 * QB);
+      const bool ok = c < nc && r < bb;
+      v[u] = (double)a[(long long)(c0 + cb + (ok ? c : 0)) * lda + i + (ok ? r : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < NCQ; ++u) {
+      const int e = tid + u * BT, c = e / (2 * QB), r = e % (2 * QB);
+      sW[r * QP + c] = (c < nc && r < bb) ? v[u] : 0.0;
+    }
   }
   if (tid < 2 * QB) sInv[tid] = (tid < bb) ? 1.0 / aget(tid, tid) : 1.0;
   stage(sQ, 0, 0, aget);

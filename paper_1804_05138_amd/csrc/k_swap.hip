@@ -3,8 +3,8 @@
 // the block's sequential transpositions; here they are applied to A (full
 // height, so rows of R already computed move too), to the permutation vector
 // and to the pending W' block.  Each workgroup owns a slab of rows and first
-// gathers every source column of its slab into LDS, then scatters, so the
-// move is a race-free permutation without a global temporary.
+// gathers every source column of its slab into registers, then scatters, so
+// the move is a race-free permutation without a global temporary.
 #include "internal.h"
 
 namespace rq {
@@ -14,18 +14,28 @@ constexpr int ST = 256;
 constexpr int SLAB = 32;  // rows per workgroup
 
 // Moves the listed columns of rows [r0, r0 + nrow) of x (leading dimension
-// ldx, column offset c0): every source first into LDS, then every destination.
+// ldx, column offset c0): the pair list goes to LDS, every source element of
+// the thread is read into registers with all loads in flight (clamped
+// addresses, masked afterwards), and after one barrier every destination is
+// written, so the move is a race-free permutation without a temporary array.
+constexpr int NPT = 2 * MAX_B * SLAB / ST;  // elements per thread at most
 template <typename S>
 RQ_DEV void move_slab(S* __restrict__ x, long long ldx, int c0, int r0, int nrow,
-                      const int* __restrict__ pairs, int np, S* buf) {
-  for (int e = threadIdx.x; e < np * SLAB; e += ST) {
-    const int p = e / SLAB, r = e % SLAB;
-    if (r < nrow) buf[e] = x[(long long)(c0 + pairs[2 * p + 1]) * ldx + r0 + r];
+                      const int* __restrict__ pairs, int np, int* spairs) {
+  for (int e = threadIdx.x; e < 2 * np; e += ST) spairs[e] = pairs[e];
+  __syncthreads();
+  S v[NPT];
+#pragma unroll
+  for (int u = 0; u < NPT; ++u) {
+    const int e = threadIdx.x + u * ST, p = e / SLAB, r = e % SLAB;
+    const bool ok = e < np * SLAB && r < nrow;
+    v[u] = x[(long long)(c0 + spairs[2 * (ok ? p : 0) + 1]) * ldx + r0 + (ok ? r : 0)];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < np * SLAB; e += ST) {
-    const int p = e / SLAB, r = e % SLAB;
-    if (r < nrow) x[(long long)(c0 + pairs[2 * p]) * ldx + r0 + r] = buf[e];
+#pragma unroll
+  for (int u = 0; u < NPT; ++u) {
+    const int e = threadIdx.x + u * ST, p = e / SLAB, r = e % SLAB;
+    if (e < np * SLAB && r < nrow) x[(long long)(c0 + spairs[2 * p]) * ldx + r0 + r] = v[u];
   }
 }
 
@@ -40,18 +50,18 @@ __global__ __launch_bounds__(ST) void k_apply_pairs(int rows, T* __restrict__ a,
                                                     int* __restrict__ jpvt,
                                                     const int* __restrict__ pairs,
                                                     const int* __restrict__ npairs) {
-  __shared__ double buf[2 * MAX_B * SLAB];
+  __shared__ int spairs[2 * 2 * MAX_B];
   const int np = *npairs;
-  if (np <= 0) return;
+  if (np <= 0 || np > 2 * MAX_B) return;
   const int g = blockIdx.x;
   if (g < na) {
     const int r0 = g * SLAB;
-    move_slab<T>(a, lda, c0, r0, min(SLAB, rows - r0), pairs, np, reinterpret_cast<T*>(buf));
+    move_slab<T>(a, lda, c0, r0, min(SLAB, rows - r0), pairs, np, spairs);
   } else if (g < na + nw) {
     const int r0 = (g - na) * SLAB;
-    move_slab<double>(wp, ldw, 0, r0, min(SLAB, wrows - r0), pairs, np, buf);
+    move_slab<double>(wp, ldw, 0, r0, min(SLAB, wrows - r0), pairs, np, spairs);
   } else if (jpvt != nullptr) {
-    move_slab<int>(jpvt, 1LL, c0, 0, 1, pairs, np, reinterpret_cast<int*>(buf));
+    move_slab<int>(jpvt, 1LL, c0, 0, 1, pairs, np, spairs);
   }
 }
 

@@ -288,6 +288,7 @@ int launch_qrcp_sketch(hipStream_t s, double* b, long long ldb, int l, int c0, i
   if (l <= 16) return launch_t<16, 1>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
   if (l <= 32) return launch_t<32, 1>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
   if (l <= 48) return launch_t<48, 1>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
+  if (l <= 72) return launch_t<36, 2>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
   if (l <= 80) return launch_t<40, 2>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
   return launch_t<40, 4>(s, bb, ldb, l, nc, nsteps, gstep0, scr, cand, pairs, info);
 }

@@ -70,7 +70,10 @@ def traffic_from_profile():
 
 def cpu_baseline(a_dev, k_sample):
     """The FP64 oracle (blocked mode) on the first k_sample columns' worth of
-    blocks of the same matrix, timed on the host."""
+    blocks of the same matrix, timed on the host.  Returns the baseline record
+    and the oracle's factorization (kept for the parity check)."""
+    import platform
+
     import numpy as np
     from oracle import rqrcp as R
     from paper_1804_05138_amd.flops import rqrcp_flops
@@ -79,15 +82,45 @@ def cpu_baseline(a_dev, k_sample):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:  # noqa: BLE001
         threads = os.cpu_count() or 1
+    cpu_model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     a_host = np.asfortranarray(a_dev.cpu().numpy())
     t0 = time.perf_counter()
-    R.rqrcp(a_host, k_sample, B, P, seed=SEED, mode="blocked")
+    f_or = R.rqrcp(a_host, k_sample, B, P, seed=SEED, mode="blocked")
     dt = time.perf_counter() - t0
     fl = rqrcp_flops(M, N, k_sample, B, P)
-    return {"value": round(fl / dt / 1e12, 5), "unit": "TFLOP/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"sketch + first {k_sample // B} blocks (k={k_sample}) of the same "
-                      f"{M}x{N} matrix, b={B}, p={P}: {fl:.3e} flop in {dt:.2f} s"}
+    rec = {"value": round(fl / dt / 1e12, 5), "unit": "TFLOP/s", "cores": int(threads),
+           "kind": "oracle", "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model,
+           "sample": f"sketch + first {k_sample // B} blocks (k={k_sample}) of the same "
+                     f"{M}x{N} matrix, b={B}, p={P}: {fl:.3e} flop in {dt:.2f} s"}
+    return rec, f_or, a_host
+
+
+def parity_sample(rq, a0, f_or, a_host, k_sample):
+    """The GPU factorization of the benchmark matrix at k = k_sample (same b, p,
+    seed) against the oracle's: identical pivots and the largest columnwise
+    error of R, V, tau, R22 and the trailing sketch."""
+    import numpy as np
+    import torch
+    from oracle.compare import factor_errors
+    f = rq.factor(a0, k_sample, B, P, seed=SEED)
+    jp = f.jpvt.cpu().numpy()
+    errs = factor_errors(a_host, k_sample, jp, f.a.cpu().numpy(), f.tau.cpu().numpy(),
+                         f_or.a, f_or.tau, f.b.cpu().numpy(), f_or.b, f_or.omega)
+    del f
+    torch.cuda.empty_cache()
+    col = {kk: float("%.3g" % v) for kk, v in errs.items() if not kk.endswith("_F")}
+    return {"k": k_sample, "pivots_equal": bool(np.array_equal(jp, f_or.jpvt)),
+            "oracle_min_rel_gap": float("%.3g" % f_or.trace.min_rel_gap()),
+            "max_columnwise_error": max(col.values()), "columnwise_error": col,
+            "bar": 1e-12}
 
 
 def _events():
@@ -265,7 +298,7 @@ def extra_backward(rq):
     for _ in range(3):
         e0, e1 = _events()
         e0.record()
-        rq.backward(a, f, dq1, dr)
+        rq.backward(a, f, dq1, dr, check=False)
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
@@ -426,7 +459,11 @@ def main():
         line["extras"] = extras
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        line["cpu_baseline"] = cpu_baseline(a0, args.cpu_sample_k)
+        line["cpu_baseline"], f_or, a_host = cpu_baseline(a0, args.cpu_sample_k)
+        log("comparing the GPU factorization of the same sample with the oracle ...")
+        line["parity"] = parity_sample(rq, a0, f_or, a_host, args.cpu_sample_k)
+        log(f"  parity: {line['parity']}")
+        del f_or, a_host
     print(json.dumps(line), flush=True)
     return 0
 

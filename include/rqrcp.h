@@ -56,6 +56,7 @@ typedef struct rqrcp_ctx *rqrcp_handle;
 #define RQRCP_ERR_LIMIT 1005       /* size beyond what the kernels accept (see rqrcp_limits) */
 #define RQRCP_ERR_BARRIER 1006     /* a persistent kernel's grid barrier timed out */
 #define RQRCP_ERR_NUMERIC 1007     /* the sketch held a non-finite value: no pivot could be chosen */
+#define RQRCP_ERR_PIVOTS 1008      /* a caller's jpvt is not a permutation of 0..n-1 */
 
 /* Element types.  A may be FP64 or FP32; the sketch B, Omega, tau and all
  * reflector arithmetic are FP64.  The sketch product may run in FP64, BF16 or
@@ -69,6 +70,9 @@ typedef struct rqrcp_ctx *rqrcp_handle;
 /* rqrcp_params.flags */
 #define RQRCP_FROZEN_PIVOTS 1u /* jpvt is an input: factor A(:, jpvt) without pivoting */
 #define RQRCP_USER_SKETCH 2u   /* B already holds the sketch Omega A (e.g. from rqrcp_sketch) */
+#define RQRCP_HOUSEHOLDER_PANEL 4u /* factor every panel one reflector at a time (Alg. 2's
+                                      panel QR as written) instead of by Cholesky-QR2 with
+                                      Householder reconstruction; slower, for comparisons */
 
 typedef struct {
   int b;           /* block size, 1 <= b <= 128 (Alg. 2 "block size b") */
@@ -78,7 +82,7 @@ typedef struct {
                       runs in FP32 and R, V are stored in FP32) */
   int sketch_type; /* arithmetic of B = Omega A: RQRCP_F64, RQRCP_BF16 or RQRCP_F8E4M3
                       (FP32 accumulation; FP8 with per-column power-of-two scales) */
-  unsigned flags;  /* RQRCP_FROZEN_PIVOTS | RQRCP_USER_SKETCH */
+  unsigned flags;  /* RQRCP_FROZEN_PIVOTS | RQRCP_USER_SKETCH | RQRCP_HOUSEHOLDER_PANEL */
 } rqrcp_params;
 
 /* Create a handle bound to `stream` (a hipStream_t; NULL = default stream)
@@ -120,7 +124,10 @@ int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, int a_type,
 /* Truncated RQRCP (Alg. 2) of the m x n matrix A to rank k, 1 <= k <= min(m, n).
  *  A     (in/out) m x n, lda, of prm->a_type: the factorization in LAPACK
  *        storage (see top).
- *  jpvt  (out) n ints; with RQRCP_FROZEN_PIVOTS an input permutation.
+ *  jpvt  (out) n ints; with RQRCP_FROZEN_PIVOTS an input permutation of
+ *        0..n-1, checked on the device before use: an entry outside [0, n)
+ *        or a repeated one sets info = -8 and makes rqrcp_check return
+ *        RQRCP_ERR_PIVOTS (A then holds no usable factorization).
  *  tau   (out) k doubles.
  *  B     (in/out) (b+p) x n sketch, ldb >= b+p.  Computed from Philox(seed)
  *        unless RQRCP_USER_SKETCH; on exit B(:, k:n) is the sketch of the
@@ -136,7 +143,9 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, v
                  size_t ws_bytes);
 
 /* Explicit Q1 = H_0 ... H_{k-1} [I_k; 0] (m x k, ldq) from a factorization
- * (A, lda, tau); b is the block size used to apply the reflectors; A and Q
+ * (A, lda, tau): the orthonormal factor of the rank-k approximation
+ * Q1 [R11 R12] Pi^T of Section I-A (eq. (1)), with Q the product of Alg. 2's
+ * panel reflectors.  b is the block size used to apply the reflectors; A and Q
  * are of a_type (RQRCP_F64 or RQRCP_F32; FP32 products on FP32 MFMA). */
 int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, int a_type, const void *A, int lda,
                  const double *tau, void *Q, int ldq, void *ws, size_t ws_bytes);
@@ -187,6 +196,8 @@ int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params *prm, doub
  * the storage precision a_type (RQRCP_F64 or RQRCP_F32).
  *  A      (in) the original m x n matrix (lda), unpivoted.
  *  AF     (in) its factorization from rqrcp_factor (ldaf, same a_type), tau, jpvt.
+ *         jpvt is checked on the device: if it is not a permutation of 0..n-1,
+ *         rqrcp_check(h, ws) returns RQRCP_ERR_PIVOTS and dA is not usable.
  *  dQ1    (in) m x k cotangent of Q1 (ldq), or NULL for zero.
  *  dR     (in) k x n cotangent of R~ in pivot order (ldr), or NULL for zero.
  *  dA     (out) m x n (ldda), original column order.
@@ -242,12 +253,21 @@ int rqrcp_autotune_batched(rqrcp_handle h, int batch, const rqrcp_problem *probs
                            void *ws, size_t ws_bytes, const float *A_orig, int *best_variant,
                            float *ms_per_variant);
 
-/* Synchronizes the handle's stream and returns RQRCP_ERR_NUMERIC if the sketch
- * QRCP found no valid pivot (a non-finite sketch; it stops pivoting, and the
- * factorization is not usable), RQRCP_ERR_BARRIER if a persistent kernel
- * reported a barrier timeout since the last check (both flags are cleared),
- * RQRCP_ERR_HIP on a HIP error, else 0.  `ws` is the workspace the kernels ran
- * with. */
+/* Synchronizes the handle's stream and returns RQRCP_ERR_PIVOTS if a caller's
+ * frozen permutation (rqrcp_factor, rqrcp_backward) was invalid,
+ * RQRCP_ERR_NUMERIC if the sketch QRCP found no valid pivot (a non-finite
+ * sketch; it stops pivoting, and the factorization is not usable),
+ * RQRCP_ERR_BARRIER if a persistent kernel reported a barrier timeout since the
+ * last check (the flags are cleared), RQRCP_ERR_HIP on a HIP error, else 0.
+ * `ws` is the workspace the kernels ran with.
+ *
+ * The persistent kernels (sketch QRCP, stepwise panel, batched) need all
+ * their workgroups resident at once.  The library checks this with the
+ * occupancy API for an otherwise idle device; other work running
+ * concurrently on the device (another stream, another process) can keep
+ * some workgroups from starting, and the bounded waits then end with
+ * RQRCP_ERR_BARRIER instead of hanging.  Run factorizations with the device
+ * to themselves. */
 int rqrcp_check(rqrcp_handle h, void *ws);
 
 /* Per-phase timing for benchmarks.  While enabled, rqrcp_factor and

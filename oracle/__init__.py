@@ -16,10 +16,12 @@ rqrcp     Alg. 1 (QRCP), Alg. 2 (RQRCP) with update formulas (1) and (2),
 srqr      Alg. 3 (spectrum-revealing swaps), exact and probed g2.
 backward  Two independent reference gradients of Q1 [R11 R12] Pi^T with the
           pivots frozen, plus central finite differences.
+compare   Column-by-column comparison of a factorization with the oracle's
+          (each column against the scale its rounding errors live on).
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` (brute force in exact rationals, LAPACK special
 cases, the paper's Kahan tables and worked example, invariants); none is
 "parity unpinned".
 """
-from . import philox, rqrcp, srqr, backward  # noqa: F401
+from . import philox, rqrcp, srqr, backward, compare  # noqa: F401

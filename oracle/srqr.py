@@ -76,8 +76,14 @@ def _g2(rhat: np.ndarray, alpha: float, exact: bool, d: int, seed: int, it: int)
 
 def srqr(a, l: int, b: int, p: int, g: float, seed: int = 0, *, d: int = 16,
          exact: bool = False, max_swaps: int | None = None, omega=None,
-         refactor: bool = True) -> SRQRResult:
-    """Alg. 3 with an l-step RQRCP (block size b, oversampling p) and tolerance g > 1."""
+         refactor: bool = True, trace: list | None = None) -> SRQRResult:
+    """Alg. 3 with an l-step RQRCP (block size b, oversampling p) and tolerance g > 1.
+
+    ``trace``: if a list, one dict per bookkeeping point is appended:
+    ``stage`` ("start", "pick", "qr", "rotate"), ``top`` (first row of the
+    trailing block the estimates refer to), copies of ``est`` and ``rw``, and
+    for "pick" the position brought to l.
+    """
     a = np.asarray(a, dtype=np.float64)
     m, n = a.shape
     if not (1 <= l < min(m, n)):
@@ -89,8 +95,20 @@ def srqr(a, l: int, b: int, p: int, g: float, seed: int = 0, *, d: int = 16,
     rw[l:, l:] = f.a[l:, l:]
     jpvt = f.jpvt.copy()
     lsk = f.b.shape[0]
+    # est[i], i >= l, estimates the squared norm of the part of column i that
+    # lies in the trailing block of rw: rows l..m-1 before the one-step QR,
+    # rows l+1..m-1 after it.  It starts from the final sketch (Section IV-E:
+    # ||B(:, i)||^2 / (b+p) estimates ||R22(:, i)||^2) and then follows the
+    # block exactly as rows leave it (the QR step removes row l) or rejoin it
+    # (a swap's rotations put a new row l in front of it).  Squared norms are
+    # never negative, so a downdate that would undershoot stops at 0.
     est = np.zeros(n)
-    est[l:] = np.sum(f.b[:, l:] ** 2, axis=0) / lsk             # r_i = ||B(:, i)||^2 / (b+p)
+    est[l:] = np.sum(f.b[:, l:] ** 2, axis=0) / lsk
+
+    def record(stage, top, pick=None):
+        if trace is not None:
+            trace.append({"stage": stage, "top": top, "est": est.copy(),
+                          "rw": rw.copy(), "pick": pick})
 
     def swap(i, j):
         if i != j:
@@ -98,16 +116,24 @@ def srqr(a, l: int, b: int, p: int, g: float, seed: int = 0, *, d: int = 16,
             jpvt[[i, j]] = jpvt[[j, i]]
             est[[i, j]] = est[[j, i]]
 
+    def bring_largest_to_l():
+        j = l + int(np.argmax(est[l:]))
+        record("pick", l, j)
+        swap(j, l)
+
     def qr_step():
-        """One-step QR of rw[l:, l:]; returns |alpha| and downdates the estimates."""
+        """One-step QR of rw[l:, l:]; row l then leaves the trailing block.
+        Returns |alpha|."""
         beta, tau, v = householder(rw[l, l], rw[l + 1:, l])
         rw[l, l] = beta
         rw[l + 1:, l] = 0.0
         apply_reflector(np.concatenate(([1.0], v)), tau, rw[l:, l + 1:])
         est[l + 1:] = np.maximum(est[l + 1:] - rw[l, l + 1:] ** 2, 0.0)
+        record("qr", l + 1)
         return abs(beta)
 
-    swap(l + int(np.argmax(est[l:])), l)
+    record("start", l)
+    bring_largest_to_l()
     alpha = qr_step()
     it = 0
     g2, cn = _g2(rw[:l + 1, :l + 1], alpha, exact, d, seed, it)
@@ -119,7 +145,6 @@ def srqr(a, l: int, b: int, p: int, g: float, seed: int = 0, *, d: int = 16,
         order = list(range(ii)) + list(range(ii + 1, l + 1)) + [ii] + list(range(l + 1, n))
         rw[:, :] = rw[:, order]
         jpvt[:] = jpvt[order]
-        est[:l + 1] = 0.0
         for j in range(ii, l):                                   # restore upper triangular R
             c, s, r = givens(rw[j, j], rw[j + 1, j])
             top = rw[j, j:].copy()
@@ -128,9 +153,13 @@ def srqr(a, l: int, b: int, p: int, g: float, seed: int = 0, *, d: int = 16,
             rw[j + 1, j:] = -s * top + c * bot
             rw[j, j] = r
             rw[j + 1, j] = 0.0
+        # the rotated row l rejoins the trailing block; column l (formerly
+        # column ii) has no entries below row l, so its estimate is exact
+        est[:l + 1] = 0.0
         est[l] = rw[l, l] ** 2
         est[l + 1:] += rw[l, l + 1:] ** 2
-        swap(l + int(np.argmax(est[l:])), l)
+        record("rotate", l)
+        bring_largest_to_l()
         alpha = qr_step()
         nswaps += 1
         it += 1

@@ -25,12 +25,14 @@ F8E4M3 = 3
 SKETCH_TYPES = {"f64": F64, "bf16": BF16, "fp8": F8E4M3}
 FROZEN_PIVOTS = 1
 USER_SKETCH = 2
+HOUSEHOLDER_PANEL = 4
 SRQR_EXACT = 1
 
 STATUS = {
     1001: "HIP runtime error", 1002: "workspace too small",
     1003: "unsupported data type combination", 1004: "device is not gfx950",
     1005: "size beyond the kernels' limits", 1006: "grid barrier timed out",
+    1007: "non-finite value in the sketch", 1008: "jpvt is not a permutation of 0..n-1",
 }
 
 # Every symbol declared in include/rqrcp.h.
@@ -250,7 +252,7 @@ class Factorization:
 
 
 def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=False,
-           check=True, sketch_type="f64"):
+           check=True, sketch_type="f64", householder_panel=False):
     """Truncated RQRCP (Alg. 2) of the FP64 or FP32 matrix ``a`` to rank ``k``.
 
     jpvt: frozen pivots (the columns A(:, jpvt) are factored without pivoting).
@@ -258,6 +260,8 @@ def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=Fal
     sketch_type: "f64", "bf16" or "fp8" (the arithmetic of B = Omega A).
     An FP32 ``a`` is the mixed-precision form (FP32 trailing update and storage,
     FP64 reflectors, sketch and sample update).
+    householder_panel: every panel one reflector at a time instead of by
+    Cholesky-QR2 (RQRCP_HOUSEHOLDER_PANEL).
     Returns a Factorization with device tensors.
     """
     torch = _torch()
@@ -273,7 +277,7 @@ def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=Fal
             af = colmajor(af)
     m, n = af.shape
     dev = af.device
-    flags = 0
+    flags = HOUSEHOLDER_PANEL if householder_panel else 0
     jp = torch.empty(n, dtype=torch.int32, device=dev)
     if jpvt is not None:
         flags |= FROZEN_PIVOTS
@@ -403,11 +407,12 @@ def srqr(a0, l, b, p, g, seed=0, *, d=16, exact=False, max_swaps=-1, sketch_b=No
     return SRQR(f.a, f.jpvt, tau, g2, ns, info)
 
 
-def backward(a, fact, dq1=None, dr=None):
+def backward(a, fact, dq1=None, dr=None, check=True):
     """dL/dA of the frozen-pivot factorization ``fact`` of ``a`` (rqrcp_backward).
 
     dq1: m x k cotangent of Q1, dr: k x n cotangent of [R11 R12] (pivot order);
     either may be None (zero).  Returns dA (m x n, original column order).
+    check: synchronize and raise if fact.jpvt was not a permutation.
     """
     torch = _torch()
     a = colmajor(a, fact.a.dtype)
@@ -427,6 +432,8 @@ def backward(a, fact, dq1=None, dr=None):
                               _ld(dq1) if dq1 is not None else m, _ptr(dr),
                               _ld(dr) if dr is not None else k, _ptr(da), _ld(da), _ptr(ws),
                               ws.numel()), "rqrcp_backward")
+    if check:
+        _check(lib.rqrcp_check(handle(), _ptr(ws)), "rqrcp_check")
     return da
 
 

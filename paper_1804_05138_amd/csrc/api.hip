@@ -93,7 +93,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t omega, sketch_part, sketch_lp, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy,
-      formq, total;
+      mark, formq, total;
 };
 
 size_t elem_size(int t) { return t == RQRCP_F32 ? sizeof(float) : sizeof(double); }
@@ -153,6 +153,7 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   L.wpart = take(wpart_doubles(m, n, k, b) * es);
   L.wp = take((size_t)b * n * sizeof(double));
   L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * es : 0);
+  L.mark = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)n * sizeof(int) : 0);
   L.formq = take(form_q_work_elems(m, k, b) * es);
   L.total = off;
   return L;
@@ -180,6 +181,9 @@ __global__ void k_init(QrcpScratch* q, PanelScratch* p, int* info, int* jpvt, in
     for (int j = t; j < n; j += gridDim.x * blockDim.x) jpvt[j] = j;
 }
 
+// dst(:, c) = src(:, perm[c]) (src(:, c) without perm), c < n.  A caller's
+// permutation is validated by k_perm_check before this runs; indices are still
+// clamped to [0, n) so that an invalid one can never address outside src.
 template <typename T>
 __global__ void k_copy_cols(int m, int n, const T* __restrict__ src, long long lds,
                             T* __restrict__ dst, long long ldd, const int* __restrict__ perm) {
@@ -187,8 +191,37 @@ __global__ void k_copy_cols(int m, int n, const T* __restrict__ src, long long l
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const long long c = e / m, r = e % m;
-    const long long sc = perm ? perm[c] : c;
+    const long long sc = perm ? (long long)min(max(perm[c], 0), n - 1) : c;
     dst[c * ldd + r] = src[sc * lds + r];
+  }
+}
+
+// Validation of a caller-supplied permutation (frozen pivots, backward):
+// k_perm_clear zeroes the n marks (and the two error words rqrcp_check reads,
+// if given), then
+// k_perm_check counts every entry; an entry outside [0, n) or one seen twice
+// sets bit 2 of the error word (rqrcp_check then returns RQRCP_ERR_PIVOTS)
+// and, if info is given, *info = info_code.
+__global__ void k_perm_clear(int n, int* __restrict__ mark, unsigned* err0, unsigned* err1) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int j = t; j < n; j += gridDim.x * blockDim.x) mark[j] = 0;
+  if (t == 0) {
+    if (err0) *err0 = 0u;
+    if (err1) *err1 = 0u;
+  }
+}
+
+__global__ void k_perm_check(int n, const int* __restrict__ perm, int* __restrict__ mark,
+                             unsigned* err, int* info, int info_code) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int j = t; j < n; j += gridDim.x * blockDim.x) {
+    const int v = perm[j];
+    bool bad = v < 0 || v >= n;
+    if (!bad) bad = atomicAdd(&mark[v], 1) != 0;
+    if (bad) {
+      atomicOr(err, 4u);
+      if (info) *info = info_code;
+    }
   }
 }
 
@@ -218,6 +251,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   const int b = prm->b, p = prm->p, l = b + p;
   (void)p;
   const bool frozen = (prm->flags & RQRCP_FROZEN_PIVOTS) != 0;
+  const bool stepwise = (prm->flags & RQRCP_HOUSEHOLDER_PANEL) != 0;
   hipStream_t s = h->stream;
   char* w = (char*)ws;
   double* om = (double*)(w + L.omega);
@@ -240,6 +274,11 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
 
   if (frozen) {
     T* cp = (T*)(w + L.copy);
+    int* mark = (int*)(w + L.mark);
+    hipLaunchKernelGGL(k_perm_clear, dim3(grid_for(n)), dim3(256), 0, s, n, mark,
+                       (unsigned*)nullptr, (unsigned*)nullptr);
+    hipLaunchKernelGGL(k_perm_check, dim3(grid_for(n)), dim3(256), 0, s, n, (const int*)jpvt,
+                       mark, &qscr->bar.err, (int*)info, -8);
     hipLaunchKernelGGL(k_copy_cols<T>, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n,
                        (const T*)A, (long long)lda, cp, (long long)m, (const int*)nullptr);
     hipLaunchKernelGGL(k_copy_cols<T>, dim3(grid_for((long long)m * n)), dim3(256), 0, s, m, n,
@@ -283,7 +322,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   }
   {
     PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m, bb, 0), 16.0 * m * (double)bb);
-    rc = launch_panel<T>(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart);
+    rc = launch_panel<T>(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart, stepwise);
     if (rc) return rc;
   }
   if (n - bb > 0) {
@@ -319,7 +358,8 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       {
         PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m - c0, bbn, bb),
                       16.0 * (m - i) * (double)bbn);
-        rc = launch_panel<T>(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart);
+        rc = launch_panel<T>(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart,
+                             stepwise);
         if (rc) return rc;
       }
       const int nrest = n - (c0 + bbn);
@@ -623,7 +663,8 @@ int rqrcp_backward_workspace_size(int m, int n, int k, int b, int a_type, size_t
   if (b < 1 || b > MAX_B) return -4;
   if (a_type != RQRCP_F64 && a_type != RQRCP_F32) return -5;
   if (!bytes) return -6;
-  *bytes = HEADER + backward_layout(m, n, k, b, elem_size(a_type)).total;
+  *bytes = HEADER + align_up((size_t)n * sizeof(int)) +
+           backward_layout(m, n, k, b, elem_size(a_type)).total;
   return 0;
 }
 
@@ -652,7 +693,18 @@ int rqrcp_backward(rqrcp_handle h, int m, int n, int k, int b, int a_type, const
   int rc = rqrcp_backward_workspace_size(m, n, k, b, a_type, &need);
   if (rc) return rc;
   if (!ws || ws_bytes < need) return RQRCP_ERR_WORKSPACE;
-  char* w = (char*)ws + HEADER;
+  {
+    int* mark = (int*)((char*)ws + HEADER);
+    // both error words rqrcp_check reads start cleared
+    unsigned* err = &((QrcpScratch*)((char*)ws + QSCR_OFF))->bar.err;
+    unsigned* err1 = &((PanelScratch*)((char*)ws + PSCR_OFF))->bar.err;
+    hipLaunchKernelGGL(k_perm_clear, dim3(grid_for(n)), dim3(256), 0, h->stream, n, mark, err,
+                       err1);
+    hipLaunchKernelGGL(k_perm_check, dim3(grid_for(n)), dim3(256), 0, h->stream, n,
+                       (const int*)jpvt, mark, err, (int*)nullptr, 0);
+    RQ_HIP_CHECK(hipGetLastError());
+  }
+  char* w = (char*)ws + HEADER + align_up((size_t)n * sizeof(int));
   if (a_type == RQRCP_F32)
     return backward<float>(h->stream, m, n, k, b, (const float*)A, lda, (const float*)AF, ldaf,
                            tau, jpvt, (const float*)dQ1, ldq, (const float*)dR, ldr, (float*)dA,
@@ -797,7 +849,9 @@ int rqrcp_check(rqrcp_handle h, void* ws) {
     const unsigned zero[3] = {0, 0, 0};
     hipMemcpy(w + QSCR_OFF, zero, sizeof(zero), hipMemcpyHostToDevice);
     hipMemcpy(w + PSCR_OFF, zero, sizeof(zero), hipMemcpyHostToDevice);
-    // bit 1 of the sketch QRCP's word: no valid pivot (a non-finite sketch)
+    // bit 2 of the first word: a caller's permutation was invalid; bit 1: the
+    // sketch QRCP found no valid pivot (a non-finite sketch)
+    if (bars[0].err & 4u) return RQRCP_ERR_PIVOTS;
     return (bars[0].err & 2u) ? RQRCP_ERR_NUMERIC : RQRCP_ERR_BARRIER;
   }
   return 0;
@@ -848,6 +902,7 @@ const char* rqrcp_status_string(int status) {
     case RQRCP_ERR_LIMIT: return "size beyond the kernels' limits";
     case RQRCP_ERR_BARRIER: return "grid barrier timed out";
     case RQRCP_ERR_NUMERIC: return "non-finite value in the sketch (no pivot could be chosen)";
+    case RQRCP_ERR_PIVOTS: return "jpvt is not a permutation of 0..n-1";
     default: return "unknown status";
   }
 }

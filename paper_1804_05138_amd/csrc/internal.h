@@ -65,11 +65,12 @@ int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* j
 // A(ip:m, i:i+bb) -= Vprev * Wp(:, 0:bb) applied first (if bbp > 0, ip = i - bbp).
 // Writes V/R in place, tau(i:i+bb) and T (bb x bb, column-major, ld bb).
 // T is the storage type of A (double or float); the arithmetic is FP64.
+// stepwise_only: one reflector at a time (no Cholesky-QR2).
 int panel_grid(int rows, int bb);
 template <typename T>
 int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
                  const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
-                 double* partial);
+                 double* partial, bool stepwise_only);
 size_t panel_partial_doubles(int rows, int bb);
 // Cholesky-QR2 panel path (k_panel_cq.hip), used by launch_panel for bb <= 64
 // and panels at least twice as tall as wide.

@@ -33,16 +33,24 @@ unsigned grid_for(long long total) {
   return (unsigned)g;
 }
 
-// dst(:, j) = src(:, perm[c0 + j]) for j < ncols (gather of pivoted columns).
+// The permutation is validated before the backward runs (an invalid one is
+// reported by rqrcp_check); gather and scatter still clamp its entries to
+// [0, n) so that no column outside the matrices is ever addressed.
+RQ_DEV long long perm_col(const int* perm, int j, int n) {
+  return (long long)min(max(perm[j], 0), n - 1);
+}
+
+// dst(:, j) = src(:, perm[c0 + j]) for j < ncols (gather of pivoted columns of
+// an m x n source).
 template <typename T>
-__global__ __launch_bounds__(BT) void k_gather(int m, int ncols, const T* __restrict__ src,
+__global__ __launch_bounds__(BT) void k_gather(int m, int n, int ncols, const T* __restrict__ src,
                                                long long lds, const int* __restrict__ perm, int c0,
                                                T* __restrict__ dst, long long ldd) {
   const long long total = (long long)m * ncols;
   for (long long e = (long long)blockIdx.x * BT + threadIdx.x; e < total;
        e += (long long)gridDim.x * BT) {
     const long long j = e / m, r = e % m;
-    dst[j * ldd + r] = src[(long long)perm[c0 + j] * lds + r];
+    dst[j * ldd + r] = src[perm_col(perm, c0 + (int)j, n) * lds + r];
   }
 }
 
@@ -55,7 +63,7 @@ __global__ __launch_bounds__(BT) void k_scatter(int m, int n, const T* __restric
   for (long long e = (long long)blockIdx.x * BT + threadIdx.x; e < total;
        e += (long long)gridDim.x * BT) {
     const long long j = e / m, r = e % m;
-    dst[(long long)perm[j] * ldd + r] = src[j * lds + r];
+    dst[perm_col(perm, (int)j, n) * ldd + r] = src[j * lds + r];
   }
 }
 
@@ -191,8 +199,8 @@ int backward(hipStream_t s, int m, int n, int k, int b, const T* a, long long ld
   rc = form_q<T>(s, m, k, b, af, ldaf, tau, q1, m, fq);
   if (rc) return rc;
   if (n2 > 0)
-    hipLaunchKernelGGL(k_gather<T>, dim3(grid_for((long long)m * n2)), dim3(BT), 0, s, m, n2, a,
-                       lda, jpvt, k, a2, (long long)m);
+    hipLaunchKernelGGL(k_gather<T>, dim3(grid_for((long long)m * n2)), dim3(BT), 0, s, m, n, n2,
+                       a, lda, jpvt, k, a2, (long long)m);
   hipLaunchKernelGGL(k_triu<T>, dim3(grid_for((long long)k * k)), dim3(BT), 0, s, k, af, ldaf, r11);
   RQ_HIP_CHECK(hipGetLastError());
   rc = launch_trinv<T>(s, k, r11, k, rinv);

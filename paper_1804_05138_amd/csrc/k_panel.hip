@@ -550,8 +550,10 @@ static int launch_stepwise(hipStream_t s, int m, T* a, long long lda, int i, int
 template <typename T>
 int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int bbp,
                  const double* wp, long long ldw, double* tau, double* t, PanelScratch* scr,
-                 double* partial) {
+                 double* partial, bool stepwise_only) {
   if (bb < 1 || bb > MAX_B || bbp < 0 || bbp > MAX_B) return RQ_ERR_LIMIT;
+  if (stepwise_only)
+    return launch_stepwise<T>(s, m, a, lda, i, bb, bbp, wp, ldw, tau, t, scr, partial, nullptr);
   // The previous block's pending update of columns i+coff .. i+coff+nc,
   // A -= V_prev W', in rank-64 pieces: piece q0 is V_prev(:, q0:q0+qb), unit
   // lower from row rp + q0, against rows q0.. of W'.
@@ -626,9 +628,9 @@ int launch_panel(hipStream_t s, int m, T* a, long long lda, int i, int bb, int b
 }
 template int launch_panel<double>(hipStream_t, int, double*, long long, int, int, int,
                                   const double*, long long, double*, double*, PanelScratch*,
-                                  double*);
+                                  double*, bool);
 template int launch_panel<float>(hipStream_t, int, float*, long long, int, int, int,
                                  const double*, long long, double*, double*, PanelScratch*,
-                                 double*);
+                                 double*, bool);
 
 }  // namespace rq

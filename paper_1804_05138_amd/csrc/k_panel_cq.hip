@@ -20,7 +20,7 @@
 // second Gram, the small-matrix step (Cholesky, modified LU, T, R), and the
 // write-back of V and R.  A flag in the scratch records whether the
 // factorization can be trusted (every Cholesky pivot positive and finite,
-// diag(R1) within a factor 1e6, the pivots of the second Gram matrix within
+// diag(R1) within a factor kCqMaxSpread, the pivots of the second Gram matrix within
 // [1/4, 4]); if not, every later kernel of this path
 // returns at once and the stepwise kernel, which reads the same flag, factors
 // the (already updated) panel instead.
@@ -28,6 +28,14 @@
 
 namespace rq {
 namespace {
+
+// Largest ratio between diagonal entries of R1 (the Cholesky factor of the
+// panel's Gram matrix) for which the Cholesky-QR2 result is used.  Measured
+// against stepwise Householder reflectors on panels graded inside one block,
+// the columnwise difference of V grows as about 3e-16 times this ratio (R and
+// tau about half that): at 1e3 it stays below 3e-13, inside the 1e-12 parity
+// bar; wider spreads go to the stepwise kernel.
+constexpr double kCqMaxSpread = 1e3;
 
 constexpr int CB = 64;        // largest panel width of this path
 constexpr int CP = CB + 1;    // LDS pitch
@@ -429,8 +437,9 @@ __global__ __launch_bounds__(ST) void k_cq_chol1(int bb, const double* __restric
   double dmin, dmax;
   const bool ok = chol_inv_pass(sG, sR, sG, bb, smult, sd, sraw, dmin, dmax);
   __syncthreads();
-  // usable if every pivot is positive and finite and diag(R1) spreads less than 1e6
-  if (threadIdx.x == 0) *flag = (ok && dmin > 1e-12 * dmax) ? 1 : 0;
+  // usable if every pivot is positive and finite and diag(R1) spreads less
+  // than kCqMaxSpread
+  if (threadIdx.x == 0) *flag = (ok && dmin * kCqMaxSpread * kCqMaxSpread > dmax) ? 1 : 0;
   for (int e = threadIdx.x; e < CB * CB; e += ST) {
     r1[e] = sR[(e / CB) * CP + (e % CB)];
     r1inv[e] = sG[(e / CB) * CP + (e % CB)];

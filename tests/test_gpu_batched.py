@@ -3,8 +3,10 @@
 Every problem j is the single-matrix Alg. 2 with Omega from Philox stream
 j + 1, run by the oracle on the same FP32-rounded matrix in FP64.  The batched
 kernel keeps A in FP32 (trailing update in FP32, reflectors and sketch in
-FP64), so results agree to FP32 accuracy and pivots agree exactly where the
-oracle's pivot decisions are separated by more than that.
+FP64), so results agree to FP32 accuracy and pivots agree exactly on every
+problem whose pivot decisions are separated by more than the FP32 rounding
+can move them (GAP below); every problem, separated or not, must satisfy the
+factorization's invariants to FP32 accuracy.
 """
 import numpy as np
 import pytest
@@ -66,9 +68,22 @@ def _rel(x, y, s=None):
     return np.linalg.norm(x - y) / (s if s > 0 else 1.0)
 
 
+# FP32 storage and trailing update perturb the trailing sketch norms by a few
+# FP32 ulps of the original column norms, amplified by at most ||A(:, j)|| over
+# the trailing norm (below 4 at k = n/8 with sigma_j = exp(-j/(n/10))): a
+# relative gap of 1e-5 between the two largest squared norms is far above that.
+GAP = 1e-5
+
+
 def test_batched_matches_oracle(rq):
+    """256 uneven problems (plus the largest and smallest allowed shapes) against
+    the single-matrix oracle: identical pivots on every problem whose pivot
+    decisions are separated by more than GAP; FP32-level agreement of R, V, tau
+    and the final sketch where the pivots agree; on every problem the
+    factorization's own invariants (A Pi = Q R and orthonormal Q) to FP32
+    accuracy."""
     import torch
-    nb = 24
+    nb = 256
     shapes = list(batch_shapes(nb, 3))
     shapes[0] = (1024, 512, 64)       # the largest problem the kernel takes
     shapes[1] = (64, 64, 8)           # the smallest
@@ -78,17 +93,24 @@ def test_batched_matches_oracle(rq):
     torch.cuda.synchronize()
     info = bt.info.cpu().numpy()
     assert np.all(info == 0), info
-    worst = {"R": 0.0, "V": 0.0, "tau": 0.0, "B": 0.0}
-    nsame = 0
+    worst = {"R": 0.0, "V": 0.0, "tau": 0.0, "B": 0.0, "res": 0.0, "orth": 0.0}
+    nsep = nsame = 0
     for j, (m, n, k) in enumerate(shapes):
         a = mats[j].astype(np.float64)
         om = P.gauss(L, m, 9, j + 1)
         f = R.rqrcp(a, k, B, PP, omega=om, mode="blocked")
         af, jp, tau, bs = _unpack(bt, j)
+        assert np.array_equal(np.sort(jp), np.arange(n)), f"problem {j}: not a permutation"
         same = np.array_equal(jp, f.jpvt)
         gap = f.trace.min_rel_gap()
-        if gap >= 1e-3:
+        if gap >= GAP:
+            nsep += 1
             assert same, f"problem {j} {shapes[j]}: pivots differ (gap {gap:.1e})"
+        q = R.form_q(af, tau, m)
+        res = np.linalg.norm(a[:, jp] - q @ R.r_factor(af, k)) / np.linalg.norm(a)
+        orth = np.linalg.norm(q[:, :k].T @ q[:, :k] - np.eye(k))
+        worst["res"] = max(worst["res"], res)
+        worst["orth"] = max(worst["orth"], orth)
         if not same:
             continue
         nsame += 1
@@ -98,8 +120,8 @@ def test_batched_matches_oracle(rq):
              "B": _rel(bs[:, k:], f.b[:, k:], np.linalg.norm(om @ a))}
         for kk, v in e.items():
             worst[kk] = max(worst[kk], v)
-    print("problems with equal pivots", nsame, "of", nb, "worst", worst)
-    assert nsame >= nb // 2
+    print("separated problems", nsep, "equal pivots", nsame, "of", nb, "worst", worst)
+    assert nsep >= nb // 2
     for kk, v in worst.items():
         assert v <= 2e-5, kk
 

@@ -15,7 +15,7 @@ import pytest
 
 from oracle import rqrcp as R
 from oracle import srqr as S
-from workloads import gaussian, kahan, lowrank
+from workloads import gaussian, kahan, kahan_embedded, lowrank
 
 
 @pytest.fixture(scope="module")
@@ -35,7 +35,7 @@ def test_kahan_table1(tables, row):
     n, k = ent["n"], ent["k"]
     kk = kahan(n, tables["setting"]["c"])
     nk = np.linalg.norm(kk)
-    # QRCP makes no interchanges on the Kahan matrix (Section VI-B)
+    # QRCP makes no interchanges on the Kahan matrix (Section V-B)
     af, _, jp = R.qrcp(kk, k)
     assert np.array_equal(jp, np.arange(n))
     assert abs(abs(af[k, k]) / nk - ent["qrcp"]) <= 5e-4 * ent["qrcp"]
@@ -125,7 +125,7 @@ def test_tau_bound_section_iv_c():
 
 
 def test_random_matrix_needs_no_swaps():
-    """Section VI-B: g2 stays modest on ordinary matrices, so no swaps."""
+    """Section IV-E: g2 stays modest on ordinary matrices, so no swaps."""
     a = lowrank(200, 160, np.exp(-np.arange(1, 161) / 20.0), 6)
     res = S.srqr(a, 30, 16, 8, 5.0, seed=2, d=16, refactor=False)
     assert res.nswaps == 0 and res.g2 <= 5.0
@@ -136,3 +136,63 @@ def test_max_swaps_cap():
     kk = kahan(n)
     res = S.srqr(kk, n - 1, 64, n - 64, 0.5, exact=True, omega=np.eye(n), max_swaps=3, refactor=False)
     assert res.nswaps == 3 and res.g2 > 0.5
+
+
+def _trailing_sq_norms(rw, top, lo):
+    return np.sum(rw[top:, lo:] ** 2, axis=0)
+
+
+def test_trailing_estimates_track_exact_norms():
+    """Alg. 3's trailing-norm estimates (Section IV-E) checked against their
+    definition.  With Omega = sqrt(m) I_m (b + p = m sketch rows) the starting
+    estimate ||B(:, i)||^2 / (b+p) is the exact squared norm of column i of the
+    trailing block, so after every QR step and every round robin the estimates
+    must equal the squared norms recomputed from the working array, and every
+    column brought to position l must be the exact argmax."""
+    m, n, nk = 80, 140, 40
+    l = nk - 1
+    a = kahan_embedded(m, n, nk, 8, c=0.4, scale=0.01)
+    tr = []
+    res = S.srqr(a, l, 8, m - 8, 1.1, exact=True, omega=np.sqrt(m) * np.eye(m),
+                 refactor=False, max_swaps=50, trace=tr)
+    assert res.nswaps >= 3
+    assert n - l - 1 >= 50
+    stages = [t["stage"] for t in tr]
+    assert stages.count("rotate") == res.nswaps and stages.count("qr") == res.nswaps + 1
+    for t in tr:
+        top = t["top"]
+        lo = top if t["stage"] != "qr" else l + 1
+        exact = _trailing_sq_norms(t["rw"], top, lo)
+        est = t["est"][lo:]
+        assert np.all(est >= 0.0)
+        assert np.max(np.abs(est - exact)) <= 1e-12 * exact.max(), t["stage"]
+        if t["stage"] == "pick":
+            srt = np.sort(exact)[::-1]
+            assert (srt[0] - srt[1]) > 1e-8 * srt[0]     # separated: the argmax is unique
+            assert t["pick"] == lo + int(np.argmax(exact))
+
+
+def test_trailing_estimate_downdate_stops_at_zero():
+    """A sketch-based estimate can be smaller than the squared entry of the row
+    that leaves the trailing block; the downdate then gives 0 (a squared norm),
+    never a negative estimate that would rank below exactly-zero columns."""
+    m, n, nk = 80, 140, 40
+    l = nk - 1
+    a = kahan_embedded(m, n, nk, 8, c=0.4, scale=0.01)
+    tr = []
+    S.srqr(a, l, 8, 4, 1.1, seed=2, exact=True, refactor=False, max_swaps=50, trace=tr)
+    undershoot = 0
+    prev = None
+    for t in tr:
+        assert np.all(t["est"] >= 0.0)
+        if t["stage"] == "qr" and prev is not None:
+            row = t["rw"][l, l + 1:]
+            before = prev["est"].copy()
+            # the pick before this QR step swapped the estimates of l and pick
+            j = prev["pick"]
+            before[[l, j]] = before[[j, l]]
+            raw = before[l + 1:] - row ** 2
+            undershoot += int(np.sum(raw < 0.0))
+            np.testing.assert_array_equal(t["est"][l + 1:], np.maximum(raw, 0.0))
+        prev = t if t["stage"] == "pick" else prev
+    assert undershoot >= 1

@@ -4,7 +4,7 @@ This module only *generates inputs*: it holds none of the factorization's
 arithmetic and is shared by the oracle tests, the GPU parity tests and the
 benchmark, so that both sides of every comparison read identical bytes.
 
-Matrix families (all from the paper's experimental setting, Section VI, which
+Matrix families (all from the paper's experimental setting, Section V, which
 uses random full-rank matrices and matrices with decaying spectra):
 
 * ``lowrank(m, n, sigma, seed)`` -- ``U diag(sigma) V^T`` with ``U``, ``V``
@@ -12,8 +12,11 @@ uses random full-rank matrices and matrices with decaying spectra):
   folded into ``Q``, Mezzadri 2007).
 * ``gaussian(m, n, seed)`` -- i.i.d. N(0, 1) entries.
 * ``kahan(n, c, s2)`` -- the Kahan matrix ``diag(s^(i-1)) (I - c N)`` of the
-  paper's pathological-matrix experiment (Section VI-B), where ``N`` is the
+  paper's pathological-matrix experiment (Section V-B), where ``N`` is the
   strictly upper triangular matrix of ones and ``s2 = s^2``.
+* ``kahan_embedded(m, n, nk, ...)`` -- a Kahan block in the top-left corner
+  next to graded Gaussian columns: QRCP keeps the Kahan columns first, so the
+  swaps of Alg. 3 have many trailing candidates to choose from.
 * ``integer_matrix`` -- small integer matrices for exact rational tests.
 
 Random streams are ``numpy.random.default_rng([family_seed, stream])``.
@@ -29,7 +32,7 @@ import numpy as np
 __all__ = [
     "rng", "haar_columns", "lowrank", "gaussian", "kahan", "integer_matrix",
     "sigma_exp", "sigma_pow", "separated_lowrank", "lowrank_torch",
-    "gaussian_torch", "batch_shapes",
+    "gaussian_torch", "batch_shapes", "kahan_embedded",
 ]
 
 
@@ -84,6 +87,17 @@ def kahan(n: int, c: float = 0.285, s2: float | None = None) -> np.ndarray:
     s = math.sqrt(s2)
     k = np.eye(n) - c * np.triu(np.ones((n, n)), 1)
     return np.asfortranarray(np.diag(s ** np.arange(n)) @ k)
+
+
+def kahan_embedded(m: int, n: int, nk: int, seed: int, c: float = 0.285,
+                   scale: float = 0.03, decay: float = 30.0) -> np.ndarray:
+    """``kahan(nk, c)`` in rows/columns 0..nk-1; columns nk..n-1 are N(0, 1)
+    scaled by ``scale * exp(-j / decay)`` (j = 0, 1, ...) over all m rows."""
+    a = np.zeros((m, n))
+    a[:nk, :nk] = kahan(nk, c)
+    a[:, nk:] = (scale * rng(seed, 7).standard_normal((m, n - nk))
+                 * np.exp(-np.arange(n - nk) / decay))
+    return np.asfortranarray(a)
 
 
 def integer_matrix(m: int, n: int, seed: int, lo: int = -9, hi: int = 9) -> np.ndarray:

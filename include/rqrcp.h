@@ -142,6 +142,24 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, v
                  int32_t *jpvt, double *tau, double *B, int ldb, int32_t *info, void *ws,
                  size_t ws_bytes);
 
+/* Tolerance-driven RQRCP: Alg. 2 run block by block until the trailing block
+ * is small enough (Section III-A notes that the method can be stopped by an
+ * error tolerance instead of a target rank).  After each block's sample update
+ * the trailing sketch B(:, c:n) equals Omega-hat_2 R22 (Section III-B, formula
+ * (1)), so ||B(:, c:n)||_F / sqrt(b+p) estimates ||R22||_F, and the initial
+ * sketch likewise estimates ||A||_F.  The loop stops after the first block
+ * whose estimate ratio is <= tol (at least one block; at most kmax columns).
+ *  tol      0 < tol < 1.
+ *  kmax     largest rank; tau holds kmax doubles, the workspace is that of
+ *           rqrcp_factor with k = kmax.
+ *  k_out    (host) the rank reached: a multiple of b, or kmax.
+ *  est_out  (host, may be NULL) the estimate ratio at k_out.
+ * Other arguments as rqrcp_factor (RQRCP_FROZEN_PIVOTS is not allowed).
+ * Synchronizes the stream once per block (the stopping test is on the host). */
+int rqrcp_factor_tol(rqrcp_handle h, int m, int n, int kmax, double tol, const rqrcp_params *prm,
+                     void *A, int lda, int32_t *jpvt, double *tau, double *B, int ldb,
+                     int32_t *info, int *k_out, double *est_out, void *ws, size_t ws_bytes);
+
 /* Explicit Q1 = H_0 ... H_{k-1} [I_k; 0] (m x k, ldq) from a factorization
  * (A, lda, tau): the orthonormal factor of the rank-k approximation
  * Q1 [R11 R12] Pi^T of Section I-A (eq. (1)), with Q the product of Alg. 2's
@@ -149,6 +167,23 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, v
  * are of a_type (RQRCP_F64 or RQRCP_F32; FP32 products on FP32 MFMA). */
 int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, int a_type, const void *A, int lda,
                  const double *tau, void *Q, int ldq, void *ws, size_t ws_bytes);
+
+/* ---- QR with column pivoting of the whole matrix (the comparator) ----
+ * Alg. 1 (Section II): at every step the column of largest trailing norm is
+ * brought forward and eliminated by a Householder reflector.  Organized as
+ * LAPACK's xGEQP3, the Level-3 form Section II describes: the trailing matrix
+ * is updated once per block of nb columns by a GEMM, but every step still reads
+ * the whole trailing matrix once (for the reflector's product with it, which
+ * the norm downdates need) -- the cost RQRCP avoids.  Trailing norms are
+ * downdated (LAPACK's rule) and recomputed exactly when a downdate has lost
+ * half the digits.  FP64 only.
+ *  A     (in/out) m x n (lda): k steps of the factorization in LAPACK storage.
+ *  jpvt  (out) n ints (the identity is the start; ties go to the lowest index).
+ *  tau   (out) k doubles.
+ * nb: 1..128.  Workspace from rqrcp_qrcp_workspace_size. */
+int rqrcp_qrcp_workspace_size(int m, int n, int k, int nb, size_t *bytes);
+int rqrcp_qrcp(rqrcp_handle h, int m, int n, int k, int nb, double *A, int lda, int32_t *jpvt,
+               double *tau, void *ws, size_t ws_bytes);
 
 /* ---- Spectrum-revealing swaps (Alg. 3, Section IV) ---- */
 #define SRQR_EXACT 1u /* g2 from the exact row norms of Rhat^-1 instead of d Gaussian probes */
@@ -182,6 +217,42 @@ int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params *prm, doub
               int max_swaps, unsigned sflags, const double *A0, int lda0, double *A, int lda,
               int32_t *jpvt, double *tau, const double *B, int ldb, double *g2_out,
               int32_t *nswaps_out, int32_t *info, void *ws, size_t ws_bytes);
+
+/* ---- Uses of a factorization: CX, CUR (Section V-D), SVD compression ----
+ * All FP64, from factorizations in LAPACK storage (rqrcp_factor, srqr_swap,
+ * rqrcp_qrcp); the library computes every product from the factors, without
+ * another pass over A.
+ *
+ * rqrcp_cx: C = A(:, jpvt[0:k]) (the k leading columns of a k-step or longer
+ * factorization AF, jpvt of A) and X = C^+ A (k x n, ldx, original column
+ * order), the minimizer of ||C X - A||_F.  From C = Q1 R11 and
+ * Q1^T A Pi = [R11 R12]: X Pi = [I | R11^-1 R12].  k <= 1024. */
+int rqrcp_cx_workspace_size(int m, int n, int k, size_t *bytes);
+int rqrcp_cx(rqrcp_handle h, int m, int n, int k, const double *AF, int ldaf,
+             const int32_t *jpvt, double *X, int ldx, void *ws, size_t ws_bytes);
+
+/* rqrcp_cur: C as in rqrcp_cx from the column factorization (AFc, jpvt_c) of
+ * the m x n A, R = A(jpvt_r[0:k], :) the rows chosen by the factorization
+ * (AFr, tau_r, jpvt_r; block size b) of A^T (n x m), and U = C^+ A R^+
+ * (k x k, ldu), the minimizer of ||C U R - A||_F: U = X Q_r1 T11^-T with X of
+ * rqrcp_cx, Q_r1 the first k columns of the row factorization's Q and T11 its
+ * leading triangle.  k <= 1024. */
+int rqrcp_cur_workspace_size(int m, int n, int k, int b, size_t *bytes);
+int rqrcp_cur(rqrcp_handle h, int m, int n, int k, int b, const double *AFc, int ldc,
+              const int32_t *jpvt_c, const double *AFr, int ldr, const double *tau_r, double *U,
+              int ldu, void *ws, size_t ws_bytes);
+
+/* rqrcp_compress: SVD compression of an l-step factorization to rank k <= l
+ * (the remark after Alg. 3; useful when SRQR ran with l > k).  With R_l the
+ * first l rows of R and U_k the k leading left singular vectors of R_l,
+ * A ~ X Y with X = Q_l U_k (m x k, ldx) and Y = U_k^T R_l Pi^T (k x n, ldy);
+ * sigma (device, k doubles, may be NULL) receives the k leading singular
+ * values of R_l.  U_k comes from the eigenvectors of R_l R_l^T (cyclic Jacobi
+ * in one workgroup): l <= 128.  tau holds at least l reflectors. */
+int rqrcp_compress_workspace_size(int m, int n, int l, int k, int b, size_t *bytes);
+int rqrcp_compress(rqrcp_handle h, int m, int n, int l, int k, int b, const double *AF, int ldaf,
+                   const double *tau, const int32_t *jpvt, double *X, int ldx, double *Y,
+                   int ldy, double *sigma, void *ws, size_t ws_bytes);
 
 /* ---- Backward of the truncated factorization with frozen pivots ----
  * The paper differentiates nothing; this is the adjoint of the map

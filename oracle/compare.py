@@ -12,8 +12,13 @@ column, each column against the scale its rounding errors live on:
   column after orthogonal transformations, so a backward-stable computation
   errs by a small multiple of u ||A(:, jpvt[j])|| in each of them.
 * V (column j < k, rows below the diagonal): the norm of the whole reflector
-  vector [1; v_j], at least 1.
-* tau: elementwise, relative to max(1, |tau_j|) (tau lies in [0, 2]).
+  vector [1; v_j] times the column's cancellation factor
+  ||A(:, jpvt[j])|| / |R_jj| (>= 1).  The reflector is built from what is left
+  of the column after j eliminations, whose entries carry absolute errors of
+  about u ||A(:, jpvt[j])|| while its norm is |R_jj|; on graded inputs any two
+  backward-stable computations of v_j differ by u times that factor.
+* tau: elementwise, relative to max(1, |tau_j|) times the same factor (tau
+  lies in [0, 2]).
 * The trailing sketch B(:, j), j >= k: the norm of the original sketch column
   (Omega A)(:, jpvt[j]), which it is computed from by orthogonal
   transformations and the update formula.
@@ -47,11 +52,14 @@ def factor_errors(a, k, jp, af_g, tau_g, af_o, tau_o, b_g=None, b_o=None, omega=
     cola = np.linalg.norm(a[:, jp], axis=0)
     r_g, r_o = np.triu(af_g[:k, :]), np.triu(af_o[:k, :])
     v_g, v_o = np.tril(af_g[:, :k], -1), np.tril(af_o[:, :k], -1)
-    vscale = np.sqrt(1.0 + np.sum(v_o ** 2, axis=0))
+    rjj = np.abs(np.diag(af_o[:k, :k]))
+    cancel = np.where(rjj > 0, cola[:k] / np.maximum(rjj, np.finfo(float).tiny), 1.0)
+    cancel = np.maximum(cancel, 1.0)
+    vscale = np.sqrt(1.0 + np.sum(v_o ** 2, axis=0)) * cancel
     errs = {
         "R": colwise(r_g, r_o, cola),
         "V": colwise(v_g, v_o, vscale),
-        "tau": float((np.abs(tau_g - tau_o) / np.maximum(1.0, np.abs(tau_o))).max()),
+        "tau": float((np.abs(tau_g - tau_o) / (np.maximum(1.0, np.abs(tau_o)) * cancel)).max()),
         "R_F": normwise(r_g, r_o),
         "V_F": normwise(v_g, v_o),
     }

@@ -201,10 +201,13 @@ class Factorization:
     info: int              # 0, or s+1 when the sketch pivot at step s was exactly 0
     omega: np.ndarray | None
     trace: StepTrace
+    k: int = 0             # rank reached (the requested k, or where stop_tol stopped)
+    est_ratio: float = 0.0  # stop_tol: sketch estimate of ||R22||_F / ||A||_F at k
 
 
 def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
-          mode: str = "plain", update: str = "formula1") -> Factorization:
+          mode: str = "plain", update: str = "formula1",
+          stop_tol: float | None = None) -> Factorization:
     """Alg. 2 on a copy of ``a`` (m x n), target rank k, block size b, oversampling p.
 
     mode = "plain": the reflectors of each panel are applied one at a time to
@@ -215,6 +218,12 @@ def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
     (Section III-B, eq. updating_2).
     omega: optional explicit (b+p) x m sketching matrix (otherwise
     Philox Omega with key (seed, 0)).
+    stop_tol: error-tolerance form (Section III-A: the loop can stop on a
+    tolerance instead of a rank).  After the sample update of each block the
+    trailing sketch B(:, i+bb:n) is Omega-hat_2 R22 (formula (1)), whose
+    Frobenius norm over sqrt(l) estimates ||R22||_F, as the first sketch's
+    estimates ||A||_F; the loop stops after the first block where the ratio
+    of the two is <= stop_tol, and k is then the rank reached.
     """
     a0 = np.asarray(a, dtype=np.float64)
     a = np.array(a0, order="F", copy=True)
@@ -227,6 +236,8 @@ def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
         l = om.shape[0]
     bsk = om @ a                                   # B = Omega A
     b_orig = bsk.copy() if update == "formula2" else None
+    norm_a_est = np.linalg.norm(bsk) / np.sqrt(l)
+    ratio = 0.0
     jpvt = np.arange(n)
     tau = np.zeros(k)
     info = 0
@@ -267,7 +278,14 @@ def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
                 q1 = form_q(a[:, :s], tau[:s])                        # m x s
                 w[:, bb:] = b_orig[:, jpvt[s:]] - (om @ q1) @ a[:s, s:]
         i += bb
-    return Factorization(a, tau, jpvt, bsk, info, om, trace)
+        if stop_tol is not None and i < n:
+            est = np.linalg.norm(bsk[:, i:]) / np.sqrt(l)
+            ratio = est / norm_a_est if norm_a_est > 0 else 0.0
+            if ratio <= stop_tol:
+                break
+    if stop_tol is not None:
+        tau = tau[:i]
+    return Factorization(a, tau, jpvt, bsk, info, om, trace, min(i, k), ratio)
 
 
 def factor_frozen(a, jpvt, k: int, b: int, mode: str = "blocked"):

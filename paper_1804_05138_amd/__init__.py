@@ -42,7 +42,9 @@ EXPORTS = (
     "rqrcp_check", "rqrcp_status_string", "rqrcp_set_timing", "rqrcp_read_timing",
     "srqr_workspace_size", "srqr_swap", "rqrcp_backward_workspace_size", "rqrcp_backward",
     "rqrcp_batched_limits", "rqrcp_batched_workspace_size", "rqrcp_factor_batched",
-    "rqrcp_autotune_batched",
+    "rqrcp_autotune_batched", "rqrcp_qrcp_workspace_size", "rqrcp_qrcp", "rqrcp_factor_tol",
+    "rqrcp_cx_workspace_size", "rqrcp_cx", "rqrcp_cur_workspace_size", "rqrcp_cur",
+    "rqrcp_compress_workspace_size", "rqrcp_compress",
 )
 PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other")
 
@@ -94,6 +96,16 @@ def load_library(path: str = LIB_PATH):
                                vp, sz]),
         "srqr_swap": (i, [vp, i, i, i, P(Params), ctypes.c_double, i, i, ctypes.c_uint,
                           vp, i, vp, i, vp, vp, vp, i, vp, vp, vp, vp, sz]),
+        "rqrcp_qrcp_workspace_size": (i, [i, i, i, i, P(sz)]),
+        "rqrcp_cx_workspace_size": (i, [i, i, i, P(sz)]),
+        "rqrcp_cx": (i, [vp, i, i, i, vp, i, vp, vp, i, vp, sz]),
+        "rqrcp_cur_workspace_size": (i, [i, i, i, i, P(sz)]),
+        "rqrcp_cur": (i, [vp, i, i, i, i, vp, i, vp, vp, i, vp, vp, i, vp, sz]),
+        "rqrcp_compress_workspace_size": (i, [i, i, i, i, i, P(sz)]),
+        "rqrcp_compress": (i, [vp, i, i, i, i, i, vp, i, vp, vp, vp, i, vp, i, vp, vp, sz]),
+        "rqrcp_factor_tol": (i, [vp, i, i, i, ctypes.c_double, P(Params), vp, i, vp, vp, vp, i,
+                                 vp, P(i), P(ctypes.c_double), vp, sz]),
+        "rqrcp_qrcp": (i, [vp, i, i, i, i, vp, i, vp, vp, vp, sz]),
         "rqrcp_status_string": (ctypes.c_char_p, [i]),
         "rqrcp_set_timing": (i, [vp, i]),
         "rqrcp_read_timing": (i, [vp, P(ctypes.c_double), P(i), P(ctypes.c_double),
@@ -307,6 +319,82 @@ def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=Fal
     return Factorization(af, jp, tau, bs, info, k, b)
 
 
+def factor_tol(a, tol, kmax, b, p, seed=0, *, sketch_b=None, ws=None, sketch_type="f64"):
+    """Tolerance-driven RQRCP (rqrcp_factor_tol): blocks of Alg. 2 until the
+    sketch estimate of ||R22||_F / ||A||_F is <= tol (at most kmax columns).
+    Returns (Factorization with k = the rank reached, estimate ratio)."""
+    torch = _torch()
+    if a.dtype not in (torch.float64, torch.float32):
+        a = a.to(torch.float64)
+    af = colmajor(a).clone(memory_format=torch.preserve_format)
+    if af.stride(0) != 1:
+        af = colmajor(af)
+    m, n = af.shape
+    dev = af.device
+    flags = 0
+    if sketch_b is not None:
+        flags |= USER_SKETCH
+        bs = colmajor(sketch_b, torch.float64).clone()
+        if bs.stride(0) != 1:
+            bs = colmajor(bs)
+    else:
+        bs = empty_colmajor(b + p, n, torch.float64, dev)
+    jp = torch.empty(n, dtype=torch.int32, device=dev)
+    tau = torch.zeros(kmax, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    at, st = _a_type(af.dtype), _sketch_type(sketch_type)
+    nbytes = workspace_bytes(m, n, kmax, b, p, flags, at, st)
+    if ws is None or ws.numel() < nbytes:
+        ws = workspace(nbytes, dev)
+    prm = Params(b, p, seed, at, st, flags)
+    kout = ctypes.c_int()
+    est = ctypes.c_double()
+    lib = load_library()
+    _check(lib.rqrcp_factor_tol(handle(), m, n, kmax, float(tol), ctypes.byref(prm), _ptr(af),
+                                _ld(af), _ptr(jp), _ptr(tau), _ptr(bs), _ld(bs), _ptr(info),
+                                ctypes.byref(kout), ctypes.byref(est), _ptr(ws), ws.numel()),
+           "rqrcp_factor_tol")
+    _check(lib.rqrcp_check(handle(), _ptr(ws)), "rqrcp_check")
+    k = kout.value
+    return Factorization(af, jp, tau[:k], bs, info, k, b), est.value
+
+
+def qrcp(a, k, nb=64, ws=None):
+    """QR with column pivoting of the whole FP64 matrix ``a`` (Alg. 1, the
+    comparator; rqrcp_qrcp): returns a Factorization (b = None)."""
+    torch = _torch()
+    af = colmajor(a, torch.float64).clone(memory_format=torch.preserve_format)
+    if af.stride(0) != 1:
+        af = colmajor(af)
+    m, n = af.shape
+    dev = af.device
+    jp = torch.empty(n, dtype=torch.int32, device=dev)
+    tau = torch.empty(k, dtype=torch.float64, device=dev)
+    lib = load_library()
+    nbytes = ctypes.c_size_t()
+    _check(lib.rqrcp_qrcp_workspace_size(m, n, k, nb, ctypes.byref(nbytes)),
+           "rqrcp_qrcp_workspace_size")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = workspace(nbytes.value, dev)
+    _check(lib.rqrcp_qrcp(handle(), m, n, k, nb, _ptr(af), _ld(af), _ptr(jp), _ptr(tau),
+                          _ptr(ws), ws.numel()), "rqrcp_qrcp")
+    return Factorization(af, jp, tau, None, None, k, nb)
+
+
+def qrcp_into(a, k, nb, jpvt, tau, ws):
+    """rqrcp_qrcp on caller-owned device buffers (no allocation, no sync)."""
+    m, n = a.shape
+    _check(load_library().rqrcp_qrcp(handle(), m, n, k, nb, _ptr(a), _ld(a), _ptr(jpvt),
+                                      _ptr(tau), _ptr(ws), ws.numel()), "rqrcp_qrcp")
+
+
+def qrcp_workspace_bytes(m, n, k, nb=64):
+    out = ctypes.c_size_t()
+    _check(load_library().rqrcp_qrcp_workspace_size(m, n, k, nb, ctypes.byref(out)),
+           "rqrcp_qrcp_workspace_size")
+    return out.value
+
+
 def factor_into(a, k, b, p, seed, jpvt, tau, bsk, info, ws, flags=0, sketch_type="f64"):
     """rqrcp_factor on caller-owned device buffers (no allocation, no sync).
 
@@ -435,6 +523,64 @@ def backward(a, fact, dq1=None, dr=None, check=True):
     if check:
         _check(lib.rqrcp_check(handle(), _ptr(ws)), "rqrcp_check")
     return da
+
+
+# ---------------------------------------------------------------------------
+# uses of a factorization: CX, CUR, SVD compression
+# ---------------------------------------------------------------------------
+
+def cx_from(fact, k=None):
+    """X = C^+ A (k x n) for C = A(:, jpvt[0:k]) from a factorization (rqrcp_cx)."""
+    torch = _torch()
+    k = fact.k if k is None else k
+    m, n = fact.a.shape
+    x = empty_colmajor(k, n, torch.float64, fact.a.device)
+    lib = load_library()
+    nb = ctypes.c_size_t()
+    _check(lib.rqrcp_cx_workspace_size(m, n, k, ctypes.byref(nb)), "rqrcp_cx_workspace_size")
+    ws = workspace(nb.value, fact.a.device)
+    _check(lib.rqrcp_cx(handle(), m, n, k, _ptr(fact.a), _ld(fact.a), _ptr(fact.jpvt), _ptr(x),
+                        k, _ptr(ws), ws.numel()), "rqrcp_cx")
+    return x
+
+
+def cur_from(fc, fr, k=None):
+    """U = C^+ A R^+ (k x k) from the column factorization ``fc`` of A and the
+    row factorization ``fr`` of A^T (rqrcp_cur); C = A(:, fc.jpvt[:k]),
+    R = A(fr.jpvt[:k], :)."""
+    torch = _torch()
+    k = fc.k if k is None else k
+    m, n = fc.a.shape
+    u = empty_colmajor(k, k, torch.float64, fc.a.device)
+    lib = load_library()
+    nb = ctypes.c_size_t()
+    _check(lib.rqrcp_cur_workspace_size(m, n, k, fr.block, ctypes.byref(nb)),
+           "rqrcp_cur_workspace_size")
+    ws = workspace(nb.value, fc.a.device)
+    _check(lib.rqrcp_cur(handle(), m, n, k, fr.block, _ptr(fc.a), _ld(fc.a), _ptr(fc.jpvt),
+                         _ptr(fr.a), _ld(fr.a), _ptr(fr.tau), _ptr(u), k, _ptr(ws), ws.numel()),
+           "rqrcp_cur")
+    return u
+
+
+def compress(fact, l, k):
+    """Rank-k SVD compression of the l-step factorization ``fact``
+    (rqrcp_compress): returns (X m x k, Y k x n, sigma) with A ~ X Y."""
+    torch = _torch()
+    m, n = fact.a.shape
+    dev = fact.a.device
+    x = empty_colmajor(m, k, torch.float64, dev)
+    y = empty_colmajor(k, n, torch.float64, dev)
+    sig = torch.empty(k, dtype=torch.float64, device=dev)
+    lib = load_library()
+    nb = ctypes.c_size_t()
+    _check(lib.rqrcp_compress_workspace_size(m, n, l, k, fact.block, ctypes.byref(nb)),
+           "rqrcp_compress_workspace_size")
+    ws = workspace(nb.value, dev)
+    _check(lib.rqrcp_compress(handle(), m, n, l, k, fact.block, _ptr(fact.a), _ld(fact.a),
+                              _ptr(fact.tau), _ptr(fact.jpvt), _ptr(x), m, _ptr(y), k, _ptr(sig),
+                              _ptr(ws), ws.numel()), "rqrcp_compress")
+    return x, y, sig
 
 
 _FN = None

@@ -93,7 +93,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t omega, sketch_part, sketch_lp, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy,
-      mark, formq, total;
+      mark, formq, est, total;
 };
 
 size_t elem_size(int t) { return t == RQRCP_F32 ? sizeof(float) : sizeof(double); }
@@ -155,6 +155,7 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * es : 0);
   L.mark = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)n * sizeof(int) : 0);
   L.formq = take(form_q_work_elems(m, k, b) * es);
+  L.est = take(4 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -227,6 +228,26 @@ __global__ void k_perm_check(int n, const int* __restrict__ perm, int* __restric
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
+// *out = ||B(0:l, c0:n)||_F^2 (one workgroup, fixed summation order).
+__global__ __launch_bounds__(1024) void k_sketch_fro2(const double* __restrict__ b, long long ldb,
+                                                      int l, int c0, int n, double* out) {
+  __shared__ double sred[16];
+  double s = 0.0;
+  const long long total = (long long)l * (n - c0);
+  for (long long e = threadIdx.x; e < total; e += 1024) {
+    const double x = b[(c0 + e / l) * ldb + e % l];
+    s += x * x;
+  }
+  s = wave_sum_dpp(s);
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += sred[w];
+    *out = t;
+  }
+}
+
 unsigned grid_for(long long total) {
   long long g = (total + 255) / 256;
   return (unsigned)std::max<long long>(1, std::min<long long>(g, 65536));
@@ -244,10 +265,27 @@ bool valid_params(const rqrcp_params* prm) {
 namespace {
 
 // The block loop of Alg. 2 for storage type T of A (see the top of the file).
+// Sketch estimate of ||A(c0:m, c0:n)'s trailing block||_F: ||B(:, c0:n)||_F / sqrt(l)
+// (formula (1) keeps B(:, c0:n) = Omega-hat_2 R22 with l Gaussian rows).
+// Synchronizes the stream.
+int sketch_estimate(hipStream_t s, const double* B, int ldb, int l, int c0, int n, double* dev,
+                    double* est) {
+  hipLaunchKernelGGL(k_sketch_fro2, dim3(1), dim3(1024), 0, s, B, (long long)ldb, l, c0, n, dev);
+  RQ_HIP_CHECK(hipGetLastError());
+  double v = 0.0;
+  RQ_HIP_CHECK(hipMemcpyAsync(&v, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  RQ_HIP_CHECK(hipStreamSynchronize(s));
+  *est = sqrt(v / l);
+  return 0;
+}
+
+// tol > 0: stop after the first block whose trailing sketch estimate is at
+// most tol times the estimate of ||A||_F (both from the sketch); *k_done (host)
+// receives the rank reached, *est_out (host) the last estimate ratio.
 template <typename T>
 int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, const Layout& L,
                 T* A, int lda, int32_t* jpvt, double* tau, double* B, int ldb, int32_t* info,
-                void* ws) {
+                void* ws, double tol = 0.0, int* k_done = nullptr, double* est_out = nullptr) {
   const int b = prm->b, p = prm->p, l = b + p;
   (void)p;
   const bool frozen = (prm->flags & RQRCP_FROZEN_PIVOTS) != 0;
@@ -305,6 +343,12 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   auto trail_flops = [&](int ii, int bbu, int bbn, int ncols) {
     return 2.0 * (m - ii) * (double)bbu * ncols + 2.0 * (m - ii - bbu) * (double)bbn * ncols;
   };
+  double* estd = (double*)(w + L.est);
+  double norm_a = 0.0, ratio = 1.0;
+  if (tol > 0.0) {
+    rc = sketch_estimate(s, B, ldb, l, 0, n, estd, &norm_a);
+    if (rc) return rc;
+  }
 
   int i = 0;
   int bb = std::min(b, k);
@@ -342,7 +386,15 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
                           ldb, c0, ncols, info);
       if (rc) return rc;
     }
-    if (c0 < k) {
+    bool stop = false;
+    if (tol > 0.0 && ncols > 0) {
+      double e = 0.0;
+      rc = sketch_estimate(s, B, ldb, l, c0, n, estd, &e);
+      if (rc) return rc;
+      ratio = norm_a > 0.0 ? e / norm_a : 0.0;
+      stop = ratio <= tol;
+    }
+    if (c0 < k && !stop) {
       const int bbn = std::min(b, k - c0);
       if (!frozen) {
         {
@@ -383,6 +435,8 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
         rc = launch_trail<T>(s, m, A, lda, i, bb, 0, wp, ldw, c0, c0, n, (T*)nullptr, 1, &dummy);
         if (rc) return rc;
       }
+      if (k_done) *k_done = c0;
+      if (est_out) *est_out = (tol > 0.0 && ncols > 0) ? ratio : 0.0;
       break;
     }
   }
@@ -525,6 +579,42 @@ int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, v
   return factor_impl<double>(h, m, n, k, prm, L, (double*)A, lda, jpvt, tau, B, ldb, info, ws);
 }
 
+int rqrcp_factor_tol(rqrcp_handle h, int m, int n, int kmax, double tol, const rqrcp_params* prm,
+                     void* A, int lda, int32_t* jpvt, double* tau, double* B, int ldb,
+                     int32_t* info, int* k_out, double* est_out, void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (kmax < 1 || kmax > std::min(m, n)) return -4;
+  if (!(tol > 0.0 && tol < 1.0)) return -5;
+  if (!valid_params(prm) || (prm->flags & RQRCP_FROZEN_PIVOTS)) return -6;
+  const int b = prm->b, p = prm->p, l = b + p;
+  if (b > MAX_B || l > MAX_L) return RQRCP_ERR_LIMIT;
+  if (!A) return -7;
+  if (lda < m) return -8;
+  if (!jpvt) return -9;
+  if (!tau) return -10;
+  if (!B) return -11;
+  if (ldb < l) return -12;
+  if (!info) return -13;
+  if (!k_out) return -14;
+  const Layout L = layout(m, n, kmax, *prm);
+  if (!ws || ws_bytes < L.total) return RQRCP_ERR_WORKSPACE;
+  int maxn = 0;
+  rqrcp_limits(l, nullptr, nullptr, &maxn);
+  if (n > maxn) return RQRCP_ERR_LIMIT;
+  double ratio = 0.0;
+  int rc;
+  if (prm->a_type == RQRCP_F32)
+    rc = factor_impl<float>(h, m, n, kmax, prm, L, (float*)A, lda, jpvt, tau, B, ldb, info, ws,
+                            tol, k_out, &ratio);
+  else
+    rc = factor_impl<double>(h, m, n, kmax, prm, L, (double*)A, lda, jpvt, tau, B, ldb, info, ws,
+                             tol, k_out, &ratio);
+  if (est_out) *est_out = ratio;
+  return rc;
+}
+
 int srqr_workspace_size(int m, int n, int l, const rqrcp_params* prm, int d, unsigned sflags,
                         size_t* bytes) {
   if (m < 1) return -1;
@@ -632,6 +722,123 @@ int srqr_swap(rqrcp_handle h, int m, int n, int l, const rqrcp_params* prm, doub
   if (nswaps_out) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, nswaps_out, nswaps);
   RQ_HIP_CHECK(hipGetLastError());
   return 0;
+}
+
+int rqrcp_qrcp_workspace_size(int m, int n, int k, int nb, size_t* bytes) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (k < 1 || k > std::min(m, n)) return -3;
+  if (nb < 1 || nb > qrcp_full_max_nb()) return -4;
+  if (!bytes) return -5;
+  *bytes = qrcp_full_workspace(m, n, k, nb);
+  return 0;
+}
+
+int rqrcp_qrcp(rqrcp_handle h, int m, int n, int k, int nb, double* A, int lda, int32_t* jpvt,
+               double* tau, void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  if (nb < 1 || nb > qrcp_full_max_nb()) return -5;
+  if (!A) return -6;
+  if (lda < m) return -7;
+  if (!jpvt) return -8;
+  if (!tau) return -9;
+  if (!ws || ws_bytes < qrcp_full_workspace(m, n, k, nb)) return RQRCP_ERR_WORKSPACE;
+  PhaseTimer pt(h, RQRCP_PHASE_OTHER, 0.0, 0.0);
+  return launch_qrcp_full(h->stream, m, n, k, nb, A, lda, (int*)jpvt, tau, (char*)ws);
+}
+
+int rqrcp_cx_workspace_size(int m, int n, int k, size_t* bytes) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (k < 1 || k > std::min(m, n)) return -3;
+  if (!bytes) return -4;
+  *bytes = HEADER + cx_workspace(n, k);
+  return 0;
+}
+
+int rqrcp_cx(rqrcp_handle h, int m, int n, int k, const double* AF, int ldaf,
+             const int32_t* jpvt, double* X, int ldx, void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  if (!AF) return -5;
+  if (ldaf < m) return -6;
+  if (!jpvt) return -7;
+  if (!X) return -8;
+  if (ldx < k) return -9;
+  if (k > 1024) return RQRCP_ERR_LIMIT;
+  if (!ws || ws_bytes < HEADER + cx_workspace(n, k)) return RQRCP_ERR_WORKSPACE;
+  return launch_cx(h->stream, m, n, k, AF, ldaf, (const int*)jpvt, X, ldx, (char*)ws + HEADER);
+}
+
+int rqrcp_cur_workspace_size(int m, int n, int k, int b, size_t* bytes) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (k < 1 || k > std::min(m, n)) return -3;
+  if (b < 1 || b > MAX_B) return -4;
+  if (!bytes) return -5;
+  *bytes = HEADER + cur_workspace(m, n, k, b);
+  return 0;
+}
+
+int rqrcp_cur(rqrcp_handle h, int m, int n, int k, int b, const double* AFc, int ldc,
+              const int32_t* jpvt_c, const double* AFr, int ldr, const double* tau_r, double* U,
+              int ldu, void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  if (b < 1 || b > MAX_B) return -5;
+  if (!AFc) return -6;
+  if (ldc < m) return -7;
+  if (!jpvt_c) return -8;
+  if (!AFr) return -9;
+  if (ldr < n) return -10;
+  if (!tau_r) return -11;
+  if (!U) return -12;
+  if (ldu < k) return -13;
+  if (k > 1024) return RQRCP_ERR_LIMIT;
+  if (!ws || ws_bytes < HEADER + cur_workspace(m, n, k, b)) return RQRCP_ERR_WORKSPACE;
+  return launch_cur(h->stream, m, n, k, b, AFc, ldc, (const int*)jpvt_c, AFr, ldr, tau_r, U, ldu,
+                    (char*)ws + HEADER);
+}
+
+int rqrcp_compress_workspace_size(int m, int n, int l, int k, int b, size_t* bytes) {
+  if (m < 1) return -1;
+  if (n < 1) return -2;
+  if (l < 1 || l > std::min(m, n)) return -3;
+  if (k < 1 || k > l) return -4;
+  if (b < 1 || b > MAX_B) return -5;
+  if (!bytes) return -6;
+  *bytes = HEADER + compress_workspace(m, n, l, k, b);
+  return 0;
+}
+
+int rqrcp_compress(rqrcp_handle h, int m, int n, int l, int k, int b, const double* AF, int ldaf,
+                   const double* tau, const int32_t* jpvt, double* X, int ldx, double* Y,
+                   int ldy, double* sigma, void* ws, size_t ws_bytes) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (l < 1 || l > std::min(m, n)) return -4;
+  if (k < 1 || k > l) return -5;
+  if (b < 1 || b > MAX_B) return -6;
+  if (!AF) return -7;
+  if (ldaf < m) return -8;
+  if (!tau) return -9;
+  if (!jpvt) return -10;
+  if (!X) return -11;
+  if (ldx < m) return -12;
+  if (!Y) return -13;
+  if (ldy < k) return -14;
+  if (l > compress_max_l()) return RQRCP_ERR_LIMIT;
+  if (!ws || ws_bytes < HEADER + compress_workspace(m, n, l, k, b)) return RQRCP_ERR_WORKSPACE;
+  return launch_compress(h->stream, m, n, l, k, b, AF, ldaf, tau, (const int*)jpvt, X, ldx, Y,
+                         ldy, sigma, (char*)ws + HEADER);
 }
 
 int rqrcp_form_q(rqrcp_handle h, int m, int k, int b, int a_type, const void* A, int lda,

@@ -26,6 +26,24 @@ template <typename T>
 int form_q(hipStream_t s, int m, int k, int b, const T* a, long long lda, const double* tau, T* q,
            long long ldq, T* work);
 
+// r11 = triu(AF(0:k, 0:k)) and rinv = r11^-1 (both dense k x k, ld k; k <= 1024).
+template <typename T>
+int upper_inverse(hipStream_t s, int k, const T* af, long long ldaf, T* r11, T* rinv);
+
+// CX, CUR and the SVD compression of a factorization (k_cur.hip), FP64.
+size_t cx_workspace(int n, int k);
+int launch_cx(hipStream_t s, int m, int n, int k, const double* af, long long ldaf,
+              const int* jpvt, double* x, long long ldx, char* ws);
+size_t cur_workspace(int m, int n, int k, int b);
+int launch_cur(hipStream_t s, int m, int n, int k, int b, const double* afc, long long ldc,
+               const int* jpc, const double* afr, long long ldr, const double* taur,
+               double* u, long long ldu, char* ws);
+int compress_max_l();
+size_t compress_workspace(int m, int n, int l, int k, int b);
+int launch_compress(hipStream_t s, int m, int n, int l, int k, int b, const double* af,
+                    long long ldaf, const double* tau, const int* jpvt, double* x, long long ldx,
+                    double* y, long long ldy, double* sigma, char* ws);
+
 // Frozen-pivot adjoint (k_backward.hip): byte offsets of its workspace.
 struct BackwardLayout {
   size_t q1, a2, qb, g, r11, rinv, mm, formq, sk, total;

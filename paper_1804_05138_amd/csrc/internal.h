@@ -131,6 +131,13 @@ int launch_batched(hipStream_t s, int variant, int batch, const rqrcp_problem* p
                    double* tpool, long long t_elems, double* bpool, long long b_elems, int* infos,
                    unsigned* queue);
 
+// Level-3 QR with column pivoting of the whole matrix (Alg. 1 organized as
+// xGEQP3; k_qrcp_full.hip): k steps, block size nb, FP64.
+size_t qrcp_full_workspace(int m, int n, int k, int nb);
+int qrcp_full_max_nb();
+int launch_qrcp_full(hipStream_t st, int m, int n, int k, int nb, double* a, long long lda,
+                     int* jpvt, double* tau, char* ws);
+
 // Explicit Q1 = H_0 ... H_{k-1} [I; 0] (m x k) from LAPACK storage.
 int launch_form_q(hipStream_t s, int m, int k, int b, const double* a, long long lda,
                   const double* tau, double* q, long long ldq, double* work);

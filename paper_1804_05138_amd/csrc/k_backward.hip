@@ -156,6 +156,15 @@ int launch_trinv(hipStream_t s, int k, const T* r, long long ldr, T* out) {
 
 }  // namespace
 
+template <typename T>
+int upper_inverse(hipStream_t s, int k, const T* af, long long ldaf, T* r11, T* rinv) {
+  hipLaunchKernelGGL(k_triu<T>, dim3(grid_for((long long)k * k)), dim3(BT), 0, s, k, af, ldaf, r11);
+  RQ_HIP_CHECK(hipGetLastError());
+  return launch_trinv<T>(s, k, r11, k, rinv);
+}
+template int upper_inverse<double>(hipStream_t, int, const double*, long long, double*, double*);
+template int upper_inverse<float>(hipStream_t, int, const float*, long long, float*, float*);
+
 BackwardLayout backward_layout(int m, int n, int k, int b, size_t es) {
   BackwardLayout L;
   size_t off = 0;

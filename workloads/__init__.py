@@ -18,6 +18,10 @@ uses random full-rank matrices and matrices with decaying spectra):
   next to graded Gaussian columns: QRCP keeps the Kahan columns first, so the
   swaps of Alg. 3 have many trailing candidates to choose from.
 * ``integer_matrix`` -- small integer matrices for exact rational tests.
+* ``rbf_kernel(n, d, seed, gamma)`` -- an n x n Gaussian (RBF) kernel matrix
+  exp(-gamma ||x_i - x_j||^2) of n seeded points in d dimensions: a stand-in
+  for the kernel matrix of the CUR/CX experiment (Section V-D, 4177 points of
+  8 features), whose data set is not used here.
 
 Random streams are ``numpy.random.default_rng([family_seed, stream])``.
 The large matrices of the benchmark can also be generated on the GPU with
@@ -32,7 +36,7 @@ import numpy as np
 __all__ = [
     "rng", "haar_columns", "lowrank", "gaussian", "kahan", "integer_matrix",
     "sigma_exp", "sigma_pow", "separated_lowrank", "lowrank_torch",
-    "gaussian_torch", "batch_shapes", "kahan_embedded",
+    "gaussian_torch", "batch_shapes", "kahan_embedded", "rbf_kernel",
 ]
 
 
@@ -98,6 +102,19 @@ def kahan_embedded(m: int, n: int, nk: int, seed: int, c: float = 0.285,
     a[:, nk:] = (scale * rng(seed, 7).standard_normal((m, n - nk))
                  * np.exp(-np.arange(n - nk) / decay))
     return np.asfortranarray(a)
+
+
+def rbf_kernel(n: int, d: int, seed: int, gamma: float = 1.0) -> np.ndarray:
+    """exp(-gamma ||x_i - x_j||^2) for n points x_i: d features, each feature an
+    N(0,1) draw scaled by a per-feature spread in [0.1, 1] (clustered, unevenly
+    scaled data rather than an isotropic cloud)."""
+    g = rng(seed, 8)
+    spread = np.linspace(0.1, 1.0, d)
+    centers = g.standard_normal((8, d)) * spread
+    x = centers[g.integers(0, 8, size=n)] + 0.3 * g.standard_normal((n, d)) * spread
+    sq = np.sum(x * x, axis=1)
+    d2 = np.maximum(sq[:, None] + sq[None, :] - 2.0 * x @ x.T, 0.0)
+    return np.asfortranarray(np.exp(-gamma * d2))
 
 
 def integer_matrix(m: int, n: int, seed: int, lo: int = -9, hi: int = 9) -> np.ndarray:

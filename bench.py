@@ -24,6 +24,8 @@ seconds of GPU time):
                p = 8, sigma_j = exp(-j/(n/10)); autotuned, HIP-graph replay
   backward     frozen-pivot adjoint of 8192 x 4096 FP32, sigma_j = 1/j, k = 256
   srqr         srqr_swap (Alg. 3, d = 16, g = 5) after the timed factorization
+  comparators  unpivoted blocked QR and QR with column pivoting of the whole
+               matrix (Alg. 1 as xGEQP3) on the timed workload, next to RQRCP
 """
 from __future__ import annotations
 
@@ -138,6 +140,61 @@ def extra_srqr(rq, a0, fact):
     dt = time.perf_counter() - t0
     return {"workload": f"{M}x{N}, l = k = {K}, d = 16, g = 5", "ms": round(dt * 1e3, 3),
             "g2": float(g2.item()), "nswaps": int(ns.item()), "info": int(info.item())}
+
+
+def extra_comparators(rq, a0, rqrcp_ms):
+    """The paper's comparison on the timed workload (Sections V-A, V-C): unpivoted
+    blocked Householder QR (frozen identity pivots) and QR with column pivoting
+    of the whole matrix (Alg. 1 as xGEQP3), k = 1024, next to RQRCP; plus
+    ||R22||_F / ||A||_F of each (how good the rank-k approximation is)."""
+    import torch
+    dev = a0.device
+    na = float(torch.linalg.norm(a0))
+    out = {"workload": f"{M}x{N}, k = {K}, block 64", "rqrcp_ms": round(rqrcp_ms, 3)}
+    # QR: rqrcp_factor with RQRCP_FROZEN_PIVOTS and jpvt = identity
+    times = []
+    for _ in range(3):
+        a = a0.t().clone().t()
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        f = rq.factor(a, K, B, P, jpvt=torch.arange(N, dtype=torch.int32, device=dev),
+                      inplace=True, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    rq.check()
+    out["qr_ms"] = round(min(times), 3)
+    out["qr_r22_rel"] = float(torch.linalg.norm(f.a[K:, K:]) / na)
+    del a, f
+    torch.cuda.empty_cache()
+    # QRCP of the whole matrix
+    a = a0.t().clone().t()
+    jp = torch.empty(N, dtype=torch.int32, device=dev)
+    tau = torch.empty(K, dtype=torch.float64, device=dev)
+    ws = rq.workspace(rq.qrcp_workspace_bytes(M, N, K, 64), dev)
+    times = []
+    for rep in range(2):
+        if rep:
+            a.copy_(a0)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        rq.qrcp_into(a, K, 64, jp, tau, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    out["qrcp_ms"] = round(min(times), 3)
+    out["qrcp_r22_rel"] = float(torch.linalg.norm(a[K:, K:]) / na)
+    out["rqrcp_over_qr"] = round(rqrcp_ms / out["qr_ms"], 3)
+    out["qrcp_over_rqrcp"] = round(out["qrcp_ms"] / rqrcp_ms, 2)
+    # the QRCP kernels are HBM-bound: one pass over the trailing matrix per pivot
+    tr_bytes = sum(8.0 * (M - j) * (N - j) for j in range(K))
+    out["qrcp_gemv_bytes"] = tr_bytes
+    out["qrcp_gbps_lower_bound"] = round(tr_bytes / (out["qrcp_ms"] / 1e3) / 1e9, 1)
+    del a, ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def extra_full_rank(rq, steps=2):
@@ -443,12 +500,15 @@ def main():
     if not args.no_extras:
         extras = {}
         f_last = rq.Factorization(copies[-1], jpvt, tau, bsk, info, K, B)
+        r22_rqrcp = float(torch.linalg.norm(copies[-1][K:, K:]) / torch.linalg.norm(a0))
         for name, fn in (("srqr", lambda: extra_srqr(rq, a0, f_last)),
+                         ("comparators", lambda: dict(extra_comparators(rq, a0, ms_step),
+                                                      rqrcp_r22_rel=r22_rqrcp)),
                          ("full_rank", lambda: extra_full_rank(rq)),
                          ("mixed", lambda: extra_mixed(rq)),
                          ("batched", lambda: extra_batched(rq)),
                          ("backward", lambda: extra_backward(rq))):
-            if name != "srqr":
+            if name not in ("srqr", "comparators"):
                 copies = None
                 f_last = None
                 torch.cuda.empty_cache()

@@ -60,7 +60,7 @@ def test_gaussian_matches_oracle(rq):
         ref = P.gauss(rows, cols, seed, stream)
         err = np.abs(om - ref) / np.maximum(1.0, np.abs(ref))
         print("Omega", (rows, cols), "max error in units of 2^-52: %.2f" % (err.max() / 2.0 ** -52))
-        assert err.max() <= 16 * 2.0 ** -52, (rows, cols, err.max())
+        assert err.max() <= 4 * 2.0 ** -52, (rows, cols, err.max())
 
 
 def test_sketch_is_omega_a(rq):

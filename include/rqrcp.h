@@ -57,6 +57,8 @@ typedef struct rqrcp_ctx *rqrcp_handle;
 #define RQRCP_ERR_BARRIER 1006     /* a persistent kernel's grid barrier timed out */
 #define RQRCP_ERR_NUMERIC 1007     /* the sketch held a non-finite value: no pivot could be chosen */
 #define RQRCP_ERR_PIVOTS 1008      /* a caller's jpvt is not a permutation of 0..n-1 */
+#define RQRCP_ERR_SCRATCH 1009     /* rqrcp_factor_noalloc: the sizes need more than
+                                      RQRCP_NOALLOC_MAX_BYTES of workspace */
 
 /* Element types.  A may be FP64 or FP32; the sketch B, Omega, tau and all
  * reflector arithmetic are FP64.  The sketch product may run in FP64, BF16 or
@@ -141,6 +143,20 @@ int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, int a_type,
 int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, void *A, int lda,
                  int32_t *jpvt, double *tau, double *B, int ldb, int32_t *info, void *ws,
                  size_t ws_bytes);
+
+/* rqrcp_factor without a workspace argument, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as rqrcp_factor; the
+ * workspace is a static device array of RQRCP_NOALLOC_MAX_BYTES bytes inside
+ * the library (one per GPU, held until the process ends).  Sizes whose
+ * rqrcp_workspace_size exceeds it return RQRCP_ERR_SCRATCH and enqueue
+ * nothing (64 MiB covers, e.g., FP64 2048 x 2048 with k = 256, b = 64, p = 8).
+ * The call allocates nothing.  Every call on one GPU shares the array, so
+ * calls that overlap on one GPU (other streams or threads) race; run them in
+ * order.  rqrcp_check(h, NULL) reads the error flags these calls leave. */
+#define RQRCP_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int rqrcp_factor_noalloc(rqrcp_handle h, int m, int n, int k, const rqrcp_params *prm, void *A,
+                         int lda, int32_t *jpvt, double *tau, double *B, int ldb, int32_t *info);
 
 /* Tolerance-driven RQRCP: Alg. 2 run block by block until the trailing block
  * is small enough (Section III-A notes that the method can be stopped by an
@@ -330,7 +346,8 @@ int rqrcp_autotune_batched(rqrcp_handle h, int batch, const rqrcp_problem *probs
  * sketch; it stops pivoting, and the factorization is not usable),
  * RQRCP_ERR_BARRIER if a persistent kernel reported a barrier timeout since the
  * last check (the flags are cleared), RQRCP_ERR_HIP on a HIP error, else 0.
- * `ws` is the workspace the kernels ran with.
+ * `ws` is the workspace the kernels ran with; NULL after rqrcp_factor_noalloc
+ * (its flags are in the static scratch), or to check for HIP errors only.
  *
  * The persistent kernels (sketch QRCP, stepwise panel, batched) need all
  * their workgroups resident at once.  The library checks this with the

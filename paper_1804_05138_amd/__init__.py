@@ -33,7 +33,9 @@ STATUS = {
     1003: "unsupported data type combination", 1004: "device is not gfx950",
     1005: "size beyond the kernels' limits", 1006: "grid barrier timed out",
     1007: "non-finite value in the sketch", 1008: "jpvt is not a permutation of 0..n-1",
+    1009: "sizes need more than the static scratch of rqrcp_factor_noalloc",
 }
+NOALLOC_MAX_BYTES = 64 << 20
 
 # Every symbol declared in include/rqrcp.h.
 EXPORTS = (
@@ -44,7 +46,7 @@ EXPORTS = (
     "rqrcp_batched_limits", "rqrcp_batched_workspace_size", "rqrcp_factor_batched",
     "rqrcp_autotune_batched", "rqrcp_qrcp_workspace_size", "rqrcp_qrcp", "rqrcp_factor_tol",
     "rqrcp_cx_workspace_size", "rqrcp_cx", "rqrcp_cur_workspace_size", "rqrcp_cur",
-    "rqrcp_compress_workspace_size", "rqrcp_compress",
+    "rqrcp_compress_workspace_size", "rqrcp_compress", "rqrcp_factor_noalloc",
 )
 PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other")
 
@@ -82,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "rqrcp_gaussian": (i, [vp, i, i, u64, u64, vp, i]),
         "rqrcp_sketch": (i, [vp, i, i, i, u64, i, vp, i, i, vp, i, vp, i, vp, sz]),
         "rqrcp_factor": (i, [vp, i, i, i, P(Params), vp, i, vp, vp, vp, i, vp, vp, sz]),
+        "rqrcp_factor_noalloc": (i, [vp, i, i, i, P(Params), vp, i, vp, vp, vp, i, vp]),
         "rqrcp_form_q": (i, [vp, i, i, i, i, vp, i, vp, vp, i, vp, sz]),
         "rqrcp_check": (i, [vp, vp]),
         "srqr_workspace_size": (i, [i, i, i, P(Params), i, ctypes.c_uint, P(sz)]),
@@ -409,6 +412,17 @@ def factor_into(a, k, b, p, seed, jpvt, tau, bsk, info, ws, flags=0, sketch_type
                                         _ptr(jpvt), _ptr(tau), _ptr(bsk),
                                         (_ld(bsk) if bsk is not None else b + p), _ptr(info),
                                         _ptr(ws), ws.numel()), "rqrcp_factor")
+
+
+def factor_noalloc_into(a, k, b, p, seed, jpvt, tau, bsk, info, flags=0, sketch_type="f64"):
+    """rqrcp_factor_noalloc on caller-owned buffers: no workspace argument, the
+    library's static device scratch instead (the call allocates nothing)."""
+    m, n = a.shape
+    prm = Params(b, p, seed, _a_type(a.dtype), _sketch_type(sketch_type), flags)
+    _check(load_library().rqrcp_factor_noalloc(handle(), m, n, k, ctypes.byref(prm), _ptr(a),
+                                                _ld(a), _ptr(jpvt), _ptr(tau), _ptr(bsk),
+                                                (_ld(bsk) if bsk is not None else b + p),
+                                                _ptr(info)), "rqrcp_factor_noalloc")
 
 
 def form_q(fact_a, tau, k=None, b=64, ws=None):

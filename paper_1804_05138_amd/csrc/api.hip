@@ -30,6 +30,10 @@
 struct rqrcp_ctx {
   hipStream_t stream;
   int device;
+  // device address of this GPU's static scratch array (rqrcp_factor_noalloc),
+  // and whether a call on this handle has used it (rqrcp_check reads its flags)
+  void* scratch = nullptr;
+  bool used_scratch = false;
   // per-phase timing (benchmarks only)
   struct Mark {
     int phase;
@@ -445,6 +449,62 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
 
 }  // namespace
 
+// ---- Static scratch of the allocation-free entry point ----
+// rqrcp_factor_noalloc takes its workspace from this file-scope device array
+// instead of a caller's buffer.  Each GPU the library runs on holds its own
+// copy until the process ends; host code must never pass the array's name to a
+// kernel (on the host it is only a stand-in): its device address is looked up
+// once per device, with that device current, when a handle is created, and
+// only that address is used.  Every call on one GPU shares the array, so calls
+// that overlap on one GPU (other streams, other threads) race.
+constexpr size_t kStaticScratchBytes = RQRCP_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= 64) return RQRCP_ERR_LIMIT;
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return RQRCP_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+// The argument checks rqrcp_factor and rqrcp_factor_noalloc share (all but the
+// workspace).
+int factor_checks(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, void* A, int lda,
+                  int32_t* jpvt, double* tau, double* B, int ldb, int32_t* info) {
+  if (!h) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (k < 1 || k > std::min(m, n)) return -4;
+  if (!valid_params(prm)) return -5;
+  const int b = prm->b, p = prm->p, l = b + p;
+  const bool frozen = (prm->flags & RQRCP_FROZEN_PIVOTS) != 0;
+  if (b > MAX_B || l > MAX_L) return RQRCP_ERR_LIMIT;
+  if (!A) return -6;
+  if (lda < m) return -7;
+  if (!jpvt) return -8;
+  if (!tau) return -9;
+  if (!frozen && !B) return -10;
+  if (!frozen && ldb < l) return -11;
+  if (!info) return -12;
+  if (!frozen) {
+    int maxn = 0;
+    rqrcp_limits(l, nullptr, nullptr, &maxn);
+    if (n > maxn) return RQRCP_ERR_LIMIT;
+  }
+  return 0;
+}
+}  // namespace
+
 extern "C" {
 
 int rqrcp_create(rqrcp_handle* h, void* stream) {
@@ -454,10 +514,15 @@ int rqrcp_create(rqrcp_handle* h, void* stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return RQRCP_ERR_HIP;
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RQRCP_ERR_DEVICE;
+  // this device's copy of the static scratch (rqrcp_factor_noalloc)
+  void* sp = nullptr;
+  const int src = scratch_address(dev, &sp);
+  if (src) return src;
   rqrcp_ctx* c = new (std::nothrow) rqrcp_ctx;
   if (!c) return RQRCP_ERR_HIP;
   c->stream = (hipStream_t)stream;
   c->device = dev;
+  c->scratch = sp;
   *h = c;
   return 0;
 }
@@ -551,32 +616,31 @@ int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, int a_type,
 int rqrcp_factor(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, void* A, int lda,
                  int32_t* jpvt, double* tau, double* B, int ldb, int32_t* info, void* ws,
                  size_t ws_bytes) {
-  if (!h) return -1;
-  if (m < 1) return -2;
-  if (n < 1) return -3;
-  if (k < 1 || k > std::min(m, n)) return -4;
-  if (!valid_params(prm)) return -5;
-  const int b = prm->b, p = prm->p, l = b + p;
-  const bool frozen = (prm->flags & RQRCP_FROZEN_PIVOTS) != 0;
-  if (b > MAX_B || l > MAX_L) return RQRCP_ERR_LIMIT;
-  if (!A) return -6;
-  if (lda < m) return -7;
-  if (!jpvt) return -8;
-  if (!tau) return -9;
-  if (!frozen && !B) return -10;
-  if (!frozen && ldb < l) return -11;
-  if (!info) return -12;
+  const int rc = factor_checks(h, m, n, k, prm, A, lda, jpvt, tau, B, ldb, info);
+  if (rc) return rc;
   const Layout L = layout(m, n, k, *prm);
   if (!ws || ws_bytes < L.total) return RQRCP_ERR_WORKSPACE;
-  if (!frozen) {
-    int maxn = 0;
-    rqrcp_limits(l, nullptr, nullptr, &maxn);
-    if (n > maxn) return RQRCP_ERR_LIMIT;
-  }
-
   if (prm->a_type == RQRCP_F32)
     return factor_impl<float>(h, m, n, k, prm, L, (float*)A, lda, jpvt, tau, B, ldb, info, ws);
   return factor_impl<double>(h, m, n, k, prm, L, (double*)A, lda, jpvt, tau, B, ldb, info, ws);
+}
+
+int rqrcp_factor_noalloc(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, void* A,
+                         int lda, int32_t* jpvt, double* tau, double* B, int ldb,
+                         int32_t* info) {
+  const int rc = factor_checks(h, m, n, k, prm, A, lda, jpvt, tau, B, ldb, info);
+  if (rc) return rc;
+  const Layout L = layout(m, n, k, *prm);
+  if (L.total > kStaticScratchBytes) return RQRCP_ERR_SCRATCH;
+  if (!h->scratch) return RQRCP_ERR_HIP;
+  h->used_scratch = true;
+  // the same kernels as rqrcp_factor, on this device's static array (its
+  // scratch words are cleared by the first kernel of every call)
+  if (prm->a_type == RQRCP_F32)
+    return factor_impl<float>(h, m, n, k, prm, L, (float*)A, lda, jpvt, tau, B, ldb, info,
+                              h->scratch);
+  return factor_impl<double>(h, m, n, k, prm, L, (double*)A, lda, jpvt, tau, B, ldb, info,
+                             h->scratch);
 }
 
 int rqrcp_factor_tol(rqrcp_handle h, int m, int n, int kmax, double tol, const rqrcp_params* prm,
@@ -1045,7 +1109,11 @@ int rqrcp_check(rqrcp_handle h, void* ws) {
   if (!h) return -1;
   if (hipStreamSynchronize(h->stream) != hipSuccess) return RQRCP_ERR_HIP;
   if (hipGetLastError() != hipSuccess) return RQRCP_ERR_HIP;
-  if (!ws) return 0;
+  if (!ws) {
+    // after rqrcp_factor_noalloc the flags live in the device's static scratch
+    if (!h->used_scratch || !h->scratch) return 0;
+    ws = h->scratch;
+  }
   char* w = (char*)ws;
   GridBarrier bars[2];
   if (hipMemcpy(&bars[0], w + QSCR_OFF, sizeof(GridBarrier), hipMemcpyDeviceToHost) != hipSuccess)
@@ -1110,6 +1178,9 @@ const char* rqrcp_status_string(int status) {
     case RQRCP_ERR_BARRIER: return "grid barrier timed out";
     case RQRCP_ERR_NUMERIC: return "non-finite value in the sketch (no pivot could be chosen)";
     case RQRCP_ERR_PIVOTS: return "jpvt is not a permutation of 0..n-1";
+    case RQRCP_ERR_SCRATCH:
+      return "the factorization needs more workspace than the static scratch of "
+             "rqrcp_factor_noalloc holds (RQRCP_NOALLOC_MAX_BYTES)";
     default: return "unknown status";
   }
 }

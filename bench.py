@@ -26,6 +26,7 @@ seconds of GPU time):
   srqr         srqr_swap (Alg. 3, d = 16, g = 5) after the timed factorization
   comparators  unpivoted blocked QR and QR with column pivoting of the whole
                matrix (Alg. 1 as xGEQP3) on the timed workload, next to RQRCP
+  tournament   the timed workload with tournament pivoting on the sketch
 """
 from __future__ import annotations
 
@@ -195,6 +196,40 @@ def extra_comparators(rq, a0, rqrcp_ms):
     del a, ws
     torch.cuda.empty_cache()
     return out
+
+
+def extra_tournament(rq, a0):
+    """The timed workload with the sketch's pivots chosen by QR with tournament
+    pivoting (RQRCP_TOURNAMENT) instead of the grid-wide partial QRCP."""
+    import torch
+    dev = a0.device
+    a = a0.t().clone().t()
+    jp = torch.empty(N, dtype=torch.int32, device=dev)
+    tau = torch.empty(K, dtype=torch.float64, device=dev)
+    bs = torch.empty((N, B + P), dtype=torch.float64, device=dev).t()
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = rq.workspace(rq.workspace_bytes(M, N, K, B, P, rq.TOURNAMENT), dev)
+    rq.factor_into(a, K, B, P, SEED, jp, tau, bs, info, ws, rq.TOURNAMENT)   # warm-up
+    rq.check(ws)
+    times = []
+    rq.set_timing(True)
+    rq.read_timing()
+    for _ in range(3):
+        a.copy_(a0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rq.factor_into(a, K, B, P, SEED, jp, tau, bs, info, ws, rq.TOURNAMENT)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ph = rq.read_timing()
+    rq.set_timing(False)
+    rq.check(ws)
+    r22 = float(torch.linalg.norm(a[K:, K:]) / torch.linalg.norm(a0))
+    del a, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"{M}x{N}, k = {K}, b = {B}, p = {P}, groups of 256, 4-way merges",
+            "ms": round(min(times), 3), "qrcp_phase_ms": round(ph["qrcp"][0] / 3, 3),
+            "r22_rel": r22, "info": int(info.item())}
 
 
 def extra_full_rank(rq, steps=2):
@@ -504,11 +539,12 @@ def main():
         for name, fn in (("srqr", lambda: extra_srqr(rq, a0, f_last)),
                          ("comparators", lambda: dict(extra_comparators(rq, a0, ms_step),
                                                       rqrcp_r22_rel=r22_rqrcp)),
+                         ("tournament", lambda: extra_tournament(rq, a0)),
                          ("full_rank", lambda: extra_full_rank(rq)),
                          ("mixed", lambda: extra_mixed(rq)),
                          ("batched", lambda: extra_batched(rq)),
                          ("backward", lambda: extra_backward(rq))):
-            if name not in ("srqr", "comparators"):
+            if name not in ("srqr", "comparators", "tournament"):
                 copies = None
                 f_last = None
                 torch.cuda.empty_cache()

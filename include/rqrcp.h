@@ -75,6 +75,12 @@ typedef struct rqrcp_ctx *rqrcp_handle;
 #define RQRCP_HOUSEHOLDER_PANEL 4u /* factor every panel one reflector at a time (Alg. 2's
                                       panel QR as written) instead of by Cholesky-QR2 with
                                       Householder reconstruction; slower, for comparisons */
+#define RQRCP_TOURNAMENT 8u  /* choose each block's pivots by QR with tournament pivoting
+                                (Section V-C's proposed replacement of the partial QRCP of
+                                B; Demmel, Grigori, Gu, Xiang 2015): Alg. 1 on groups of
+                                256 sketch columns, nominations merged four sets at a time
+                                by Alg. 1 until one set is left, then the sketch block
+                                factored with those pivots; b <= 64, b + p <= 80 */
 
 typedef struct {
   int b;           /* block size, 1 <= b <= 128 (Alg. 2 "block size b") */
@@ -84,7 +90,8 @@ typedef struct {
                       runs in FP32 and R, V are stored in FP32) */
   int sketch_type; /* arithmetic of B = Omega A: RQRCP_F64, RQRCP_BF16 or RQRCP_F8E4M3
                       (FP32 accumulation; FP8 with per-column power-of-two scales) */
-  unsigned flags;  /* RQRCP_FROZEN_PIVOTS | RQRCP_USER_SKETCH | RQRCP_HOUSEHOLDER_PANEL */
+  unsigned flags;  /* RQRCP_FROZEN_PIVOTS | RQRCP_USER_SKETCH | RQRCP_HOUSEHOLDER_PANEL |
+                      RQRCP_TOURNAMENT */
 } rqrcp_params;
 
 /* Create a handle bound to `stream` (a hipStream_t; NULL = default stream)

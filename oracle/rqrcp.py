@@ -123,6 +123,99 @@ def partial_qrcp(w: np.ndarray, nsteps: int, trace: StepTrace | None = None):
     return pivots, rank_stop
 
 
+# ---------------------------------------------------------------------------
+# Tournament pivoting on the sketch (the first future-work item of Section V-C:
+# QR with tournament pivoting in place of the partial QRCP of B)
+# ---------------------------------------------------------------------------
+
+def _qrcp_choose(w: np.ndarray, nsteps: int, trace: StepTrace | None = None) -> list:
+    """Positions (within w) chosen by nsteps greedy steps of Alg. 1 on a copy of
+    w (norms recomputed, ties to the lowest position), in the order chosen.
+    Stops early when every remaining norm is exactly zero."""
+    w = np.array(w, dtype=np.float64, copy=True)
+    rows, ncols = w.shape
+    order = list(range(ncols))
+    chosen = []
+    for t in range(min(nsteps, ncols)):
+        norms = np.sqrt(np.sum(w[t:, t:] ** 2, axis=0)) if t < rows else np.zeros(ncols - t)
+        j = t + int(np.argmax(norms))
+        if norms[j - t] == 0.0:
+            break
+        if trace is not None:
+            sq = np.sort(norms ** 2)[::-1]
+            trace.top2.append((sq[0], sq[1] if sq.size > 1 else 0.0))
+        if j != t:
+            w[:, [t, j]] = w[:, [j, t]]
+            order[t], order[j] = order[j], order[t]
+        chosen.append(order[t])
+        if t < rows:
+            beta, tau, v = householder(w[t, t], w[t + 1:, t])
+            w[t, t] = beta
+            w[t + 1:, t] = 0.0
+            apply_reflector(np.concatenate(([1.0], v)), tau, w[t:, t + 1:])
+    return chosen
+
+
+def tournament_choose(w: np.ndarray, nsteps: int, group: int,
+                      trace: StepTrace | None = None, fanout: int = 2) -> list:
+    """QR with tournament pivoting (Demmel, Grigori, Gu and Xiang, 2015) on the
+    columns of w: the columns are split into consecutive groups of ``group``;
+    each group nominates up to nsteps columns by Alg. 1; nominations are then
+    merged ``fanout`` sets at a time (sets fanout*i .. fanout*i + fanout - 1,
+    concatenated in order; a last chunk holding a single set passes to the
+    next round unchanged), each merged set again reduced to nsteps columns by
+    Alg. 1, until one set is left.  Returns its columns (positions within w)
+    in the order the last Alg. 1 run chose them."""
+    ncols = w.shape[1]
+    sets = [list(range(s, min(s + group, ncols))) for s in range(0, ncols, group)]
+    # every selection decision (leaves and merges) is recorded in the trace
+    sets = [[c[j] for j in _qrcp_choose(w[:, c], nsteps, trace)] for c in sets]
+    while len(sets) > 1:
+        merged = []
+        for g in range(0, len(sets), fanout):
+            chunk = sets[g:g + fanout]
+            if len(chunk) == 1:
+                merged.append(chunk[0])
+                continue
+            u = [c for st in chunk for c in st]
+            merged.append([u[j] for j in _qrcp_choose(w[:, u], nsteps, trace)])
+        sets = merged
+    return sets[0]
+
+
+def transpositions(winners: list) -> list:
+    """LAPACK-style transpositions (t, p_t), t = 0, 1, ..., that bring the
+    columns at positions winners[0], winners[1], ... to positions 0, 1, ...,
+    applied in order."""
+    pos = list(range(max(winners + [len(winners) - 1]) + 1))   # position -> column
+    where = {c: c for c in pos}                                  # column -> position
+    out = []
+    for t, c in enumerate(winners):
+        p = where[c]
+        out.append((t, p))
+        if p != t:
+            ct = pos[t]
+            pos[t], pos[p] = c, ct
+            where[c], where[ct] = t, p
+    return out
+
+
+def partial_qr_fixed(w: np.ndarray, pivots_tp: list) -> None:
+    """Apply the transpositions to the columns of w, then Householder steps on
+    the first len(pivots_tp) columns (no further pivoting), in place."""
+    rows = w.shape[0]
+    for t, p in pivots_tp:
+        if p != t:
+            w[:, [t, p]] = w[:, [p, t]]
+    for t in range(len(pivots_tp)):
+        if t >= rows:
+            break
+        beta, tau, v = householder(w[t, t], w[t + 1:, t])
+        w[t, t] = beta
+        w[t + 1:, t] = 0.0
+        apply_reflector(np.concatenate(([1.0], v)), tau, w[t:, t + 1:])
+
+
 def qrcp(a: np.ndarray, k: int, trace: StepTrace | None = None):
     """Alg. 1 (deterministic QRCP) to k steps on a copy of ``a``.
 
@@ -207,7 +300,8 @@ class Factorization:
 
 def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
           mode: str = "plain", update: str = "formula1",
-          stop_tol: float | None = None) -> Factorization:
+          stop_tol: float | None = None, tournament: int | None = None,
+          fanout: int = 2) -> Factorization:
     """Alg. 2 on a copy of ``a`` (m x n), target rank k, block size b, oversampling p.
 
     mode = "plain": the reflectors of each panel are applied one at a time to
@@ -224,6 +318,11 @@ def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
     Frobenius norm over sqrt(l) estimates ||R22||_F, as the first sketch's
     estimates ||A||_F; the loop stops after the first block where the ratio
     of the two is <= stop_tol, and k is then the rank reached.
+    tournament: group size of QR with tournament pivoting used in place of
+    the partial QRCP of the sketch (``tournament_choose``, merging ``fanout``
+    sets at a time); the chosen columns
+    are brought to the front in order and the sketch block is then factored
+    by Householder steps without further pivoting.
     """
     a0 = np.asarray(a, dtype=np.float64)
     a = np.array(a0, order="F", copy=True)
@@ -246,7 +345,17 @@ def rqrcp(a, k: int, b: int, p: int, seed: int = 0, *, omega=None,
     while i < k:
         bb = min(b, k - i)
         w = bsk[:, i:]                             # view: partial QRCP acts on B(:, i:n)
-        if info == 0:
+        if info == 0 and tournament is not None:
+            win = tournament_choose(w, bb, tournament, trace, fanout)
+            tp = transpositions(win)
+            partial_qr_fixed(w, tp)
+            for t, j in tp:                        # same transpositions on A and Pi
+                if j != t:
+                    a[:, [i + t, i + j]] = a[:, [i + j, i + t]]
+                    jpvt[[i + t, i + j]] = jpvt[[i + j, i + t]]
+            if len(win) < bb:                      # every remaining sketch column was zero
+                info = i + len(win) + 1
+        elif info == 0:
             pivots, rank_stop = partial_qrcp(w, bb, trace)
             for t, j in enumerate(pivots):         # same transpositions on A and Pi
                 if j != t:

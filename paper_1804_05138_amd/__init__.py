@@ -26,6 +26,9 @@ SKETCH_TYPES = {"f64": F64, "bf16": BF16, "fp8": F8E4M3}
 FROZEN_PIVOTS = 1
 USER_SKETCH = 2
 HOUSEHOLDER_PANEL = 4
+TOURNAMENT = 8
+TOURNAMENT_GROUP = 256
+TOURNAMENT_FANOUT = 4
 SRQR_EXACT = 1
 
 STATUS = {
@@ -267,7 +270,7 @@ class Factorization:
 
 
 def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=False,
-           check=True, sketch_type="f64", householder_panel=False):
+           check=True, sketch_type="f64", householder_panel=False, tournament=False):
     """Truncated RQRCP (Alg. 2) of the FP64 or FP32 matrix ``a`` to rank ``k``.
 
     jpvt: frozen pivots (the columns A(:, jpvt) are factored without pivoting).
@@ -277,6 +280,8 @@ def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=Fal
     FP64 reflectors, sketch and sample update).
     householder_panel: every panel one reflector at a time instead of by
     Cholesky-QR2 (RQRCP_HOUSEHOLDER_PANEL).
+    tournament: pivots by QR with tournament pivoting on the sketch
+    (RQRCP_TOURNAMENT; groups of 256 columns, four-way merges).
     Returns a Factorization with device tensors.
     """
     torch = _torch()
@@ -292,7 +297,7 @@ def factor(a, k, b, p, seed=0, *, jpvt=None, sketch_b=None, ws=None, inplace=Fal
             af = colmajor(af)
     m, n = af.shape
     dev = af.device
-    flags = HOUSEHOLDER_PANEL if householder_panel else 0
+    flags = (HOUSEHOLDER_PANEL if householder_panel else 0) | (TOURNAMENT if tournament else 0)
     jp = torch.empty(n, dtype=torch.int32, device=dev)
     if jpvt is not None:
         flags |= FROZEN_PIVOTS

@@ -97,7 +97,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t omega, sketch_part, sketch_lp, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy,
-      mark, formq, est, total;
+      mark, formq, est, tourn, total;
 };
 
 size_t elem_size(int t) { return t == RQRCP_F32 ? sizeof(float) : sizeof(double); }
@@ -160,6 +160,7 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   L.mark = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)n * sizeof(int) : 0);
   L.formq = take(form_q_work_elems(m, k, b) * es);
   L.est = take(4 * sizeof(double));
+  L.tourn = take((flags & RQRCP_TOURNAMENT) ? tournament_bytes(n) : 0);
   L.total = off;
   return L;
 }
@@ -348,6 +349,14 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     return 2.0 * (m - ii) * (double)bbu * ncols + 2.0 * (m - ii - bbu) * (double)bbn * ncols;
   };
   double* estd = (double*)(w + L.est);
+  // partial QRCP of B(:, c0:c0+nc) for nsteps pivots: the grid-wide greedy
+  // kernel, or tournament pivoting
+  auto qrcp_block = [&](int c0q, int ncq, int nsteps, int gstep0) -> int {
+    if (prm->flags & RQRCP_TOURNAMENT)
+      return launch_qrcp_tournament(s, B, ldb, l, c0q, ncq, nsteps, gstep0, qscr, pairs, info,
+                                    w + L.tourn);
+    return launch_qrcp_sketch(s, B, ldb, l, c0q, ncq, nsteps, gstep0, qscr, cand, pairs, info);
+  };
   double norm_a = 0.0, ratio = 1.0;
   if (tol > 0.0) {
     rc = sketch_estimate(s, B, ldb, l, 0, n, estd, &norm_a);
@@ -360,7 +369,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   if (!frozen) {
     {
       PhaseTimer pt(h, RQRCP_PHASE_QRCP, qrcp_flops(n, bb), 16.0 * l * (double)n);
-      rc = launch_qrcp_sketch(s, B, ldb, l, 0, n, bb, 0, qscr, cand, pairs, info);
+      rc = qrcp_block(0, n, bb, 0);
       if (rc) return rc;
     }
     PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
@@ -403,7 +412,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       if (!frozen) {
         {
           PhaseTimer pt(h, RQRCP_PHASE_QRCP, qrcp_flops(ncols, bbn), 16.0 * l * (double)ncols);
-          rc = launch_qrcp_sketch(s, B, ldb, l, c0, ncols, bbn, c0, qscr, cand, pairs, info);
+          rc = qrcp_block(c0, ncols, bbn, c0);
           if (rc) return rc;
         }
         PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
@@ -501,6 +510,8 @@ int factor_checks(rqrcp_handle h, int m, int n, int k, const rqrcp_params* prm, 
     rqrcp_limits(l, nullptr, nullptr, &maxn);
     if (n > maxn) return RQRCP_ERR_LIMIT;
   }
+  if ((prm->flags & RQRCP_TOURNAMENT) && (b > tournament_max_b() || l > tournament_max_l()))
+    return RQRCP_ERR_LIMIT;
   return 0;
 }
 }  // namespace
@@ -667,6 +678,8 @@ int rqrcp_factor_tol(rqrcp_handle h, int m, int n, int kmax, double tol, const r
   int maxn = 0;
   rqrcp_limits(l, nullptr, nullptr, &maxn);
   if (n > maxn) return RQRCP_ERR_LIMIT;
+  if ((prm->flags & RQRCP_TOURNAMENT) && (b > tournament_max_b() || l > tournament_max_l()))
+    return RQRCP_ERR_LIMIT;
   double ratio = 0.0;
   int rc;
   if (prm->a_type == RQRCP_F32)

@@ -54,6 +54,15 @@ int launch_qrcp_sketch(hipStream_t s, double* b, long long ldb, int l, int c0, i
                        int* info);
 size_t qrcp_cand_doubles(int l, int nc);
 
+// QR with tournament pivoting in place of launch_qrcp_sketch (same outputs):
+// b <= tournament_max_b(), l <= tournament_max_l(); ws of tournament_bytes(n).
+size_t tournament_bytes(int n);
+int tournament_max_b();
+int tournament_max_l();
+int launch_qrcp_tournament(hipStream_t s, double* b, long long ldb, int l, int c0, int nc,
+                           int nsteps, int gstep0, QrcpScratch* scr, int* pairs, int* info,
+                           char* ws);
+
 // Column moves from `pairs` (count at *npairs) applied to A(0:m, c0 + .),
 // jpvt(c0 + .) and W'(0:wrows, w0 + .) (W' may be null).
 template <typename T>

@@ -27,6 +27,7 @@ seconds of GPU time):
   comparators  unpivoted blocked QR and QR with column pivoting of the whole
                matrix (Alg. 1 as xGEQP3) on the timed workload, next to RQRCP
   tournament   the timed workload with tournament pivoting on the sketch
+  cur          SRQR-based CX and CUR of a 4177 x 4177 RBF kernel matrix, k = l = 200
 """
 from __future__ import annotations
 
@@ -232,6 +233,43 @@ def extra_tournament(rq, a0):
             "r22_rel": r22, "info": int(info.item())}
 
 
+def extra_cur(rq):
+    """SRQR-based CX and CUR (Section V-D) on a synthetic RBF kernel matrix of the
+    experiment's size (4177 points, 8 features; k = l = 200, b = 64, p = 10, g = 5)."""
+    import numpy as np
+    import torch
+    from workloads import rbf_kernel
+    n, k = 4177, 200
+    a_h = rbf_kernel(n, 8, 1, 1.0)
+    a = torch.from_numpy(np.ascontiguousarray(a_h.T)).cuda().t()
+    del a_h
+    rq.srqr(a, k, 64, 10, 5.0, seed=1)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc = rq.srqr(a, k, 64, 10, 5.0, seed=1)
+    at = rq.colmajor(a.t())
+    sr = rq.srqr(at, k, 64, 10, 5.0, seed=2)
+    fc = rq.Factorization(sc.a, sc.jpvt, sc.tau, None, None, k, 64)
+    fr = rq.Factorization(sr.a, sr.jpvt, sr.tau, None, None, k, 64)
+    x = rq.cx_from(fc, k)
+    u = rq.cur_from(fc, fr, k)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    cols = sc.jpvt[:k].long()
+    rows = sr.jpvt[:k].long()
+    c = a[:, cols]
+    r = a[rows, :]
+    na = torch.linalg.norm(a)
+    res_cx = float(torch.linalg.norm(a - c @ x) / na)
+    res_cur = float(torch.linalg.norm(a - c @ u @ r) / na)
+    sv = torch.linalg.svdvals(a)
+    best = float(torch.sqrt(torch.sum(sv[k:] ** 2)) / na)
+    return {"workload": "RBF kernel 4177x4177 (8 features), k = l = 200, b = 64, p = 10, g = 5",
+            "ms_srqr_cols_rows_cx_cur": round(ms, 3), "residual_cx": res_cx,
+            "residual_cur": res_cur, "best_rank_k": best,
+            "swaps_cols": int(sc.nswaps.item()), "swaps_rows": int(sr.nswaps.item())}
+
+
 def extra_full_rank(rq, steps=2):
     """FP64 RQRCP of a 32768 x 8192 i.i.d. N(0,1) matrix to full rank k = 8192."""
     import torch
@@ -422,6 +460,9 @@ def main():
                          "for profiler runs, where kernel times depend only on the sizes)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the measurements of the other forms")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated subset of: srqr, comparators, tournament, cur, "
+                         "full_rank, mixed, batched, backward (default all)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain elementwise copy of this many MiB "
                          "(FP64), whose HBM counters calibrate the trailing update's")
@@ -540,11 +581,14 @@ def main():
                          ("comparators", lambda: dict(extra_comparators(rq, a0, ms_step),
                                                       rqrcp_r22_rel=r22_rqrcp)),
                          ("tournament", lambda: extra_tournament(rq, a0)),
+                         ("cur", lambda: extra_cur(rq)),
                          ("full_rank", lambda: extra_full_rank(rq)),
                          ("mixed", lambda: extra_mixed(rq)),
                          ("batched", lambda: extra_batched(rq)),
                          ("backward", lambda: extra_backward(rq))):
-            if name not in ("srqr", "comparators", "tournament"):
+            if args.extras != "all" and name not in args.extras.split(","):
+                continue
+            if name not in ("srqr", "comparators", "tournament", "cur"):
                 copies = None
                 f_last = None
                 torch.cuda.empty_cache()

@@ -318,7 +318,8 @@ typedef struct {
 } rqrcp_problem;
 
 /* Limits of the batched kernel (host outputs): m <= max_m, (b+p) n <= max_ln,
- * n <= 1024, b <= max_b, b + p <= max_l. */
+ * n <= 1024, b <= max_b, b + p <= max_l; a problem's extent (n-1) lda + m is
+ * below 2^31 elements. */
 int rqrcp_batched_limits(int *max_m, int *max_ln, int *max_b, int *max_l);
 int rqrcp_batched_workspace_size(size_t *bytes);
 /* Factor `batch` problems in place (A_j -> R, V, R22 in LAPACK storage).

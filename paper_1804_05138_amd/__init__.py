@@ -715,7 +715,7 @@ def autotune_batched(batch: Batch, a_orig, b, p, seed=0):
         batch.a.numel(), _ptr(batch.jpvt), batch.jpvt.numel(), _ptr(batch.tau),
         batch.tau.numel(), _ptr(batch.b), batch.b.numel(), _ptr(batch.info), _ptr(batch.ws),
         batch.ws.numel(), _ptr(a_orig), ctypes.byref(best), ms), "rqrcp_autotune_batched")
-    return best.value, [ms[v] for v in range(2)]
+    return best.value, [x for x in ms if x > 0.0]
 
 
 def batched_limits():

@@ -5,14 +5,15 @@
 //
 // Per problem everything but A stays on chip:
 //   * the sketch B = Omega A (l x n, FP64) lives in LDS for the whole
-//     factorization; Omega (Philox stream problem + 1) is regenerated in
-//     64-row chunks while A is streamed once;
+//     factorization; it is formed on FP64 MFMA (16x16x4) with Omega (Philox
+//     stream problem + 1) regenerated in 64-row chunks while A is streamed once;
 //   * the partial QRCP of B (Alg. 1, norms recomputed) runs on LDS;
 //   * the panel (rows i..m-1, bb <= 16 columns) is held in registers in FP64,
 //     one reduction of 16 dot products per reflector;
-//   * the trailing update A2 -= V (T^T (V^T A2)) streams A2 through L2 in FP32
-//     (V staged in LDS by row chunks, one thread per column), and formula (1)
-//     refreshes that column of B right after its update.
+//   * the trailing update A2 -= V (T^T (V^T A2)) runs on FP32 MFMA, one wave
+//     per 16-column tile with its row loads double-buffered in registers;
+//     T^T W and formula (1) (B(0:bb, tile) -= Rhat11 R11^-1 R12) are FP64 MFMA
+//     products on the tile's registers.
 // A is FP32 (the batched form is the mixed-precision one); reflectors, T, the
 // sketch and its updates are FP64.
 #include <limits.h>
@@ -33,6 +34,7 @@ struct BatchedSmem {
   double t[BMAX * BMAX];
   double r11[BMAX * BMAX];
   double gz[BMAX * BMAX];
+  double mm[BMAX * BMAX];  // M = Rhat11 R11^-1 of formula (1), row-major
   double red[16 * BMAX];  // per-wave partial sums (up to 16 waves)
   double row[BMAX];
   double s[BMAX];
@@ -46,9 +48,8 @@ struct BatchedSmem {
   int problem;
   int dead;               // a zero sketch pivot was met (no more pivoting or updates)
   int info;
-  // sketch phase: Omega chunk (RC x LMAX doubles); trailing phase: V chunk
-  // (NT x BMAX floats)
-  __attribute__((aligned(16))) char chunk[32768];
+  // sketch phase: Omega chunk (RC x LMAX doubles)
+  __attribute__((aligned(16))) char chunk[RC * LMAX * 8];
 };
 
 // Values every thread of the workgroup holds identically (read back from LDS
@@ -86,6 +87,8 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
     int* __restrict__ infos, unsigned* __restrict__ queue) {
   constexpr int RPT = MMAX / NT;
   constexpr int NW = NT / 64;
+  constexpr int SKT = 4;                  // 16-column tiles per wave in the sketch
+  constexpr int TG = NT >= 512 ? 1 : 2;   // 16-row steps per load group (trailing update)
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   BatchedSmem& S = *reinterpret_cast<BatchedSmem*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -104,6 +107,7 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
     // does not fit the kernel or the pools
     const bool ok = m >= 1 && n >= 1 && k >= 1 && k <= min(m, n) && m <= MMAX && n <= 1024 &&
                     (long long)l * n <= SB_DOUBLES && lda >= m && pr.a_off >= 0 &&
+                    (long long)(n - 1) * lda + m <= (long long)INT_MAX &&
                     pr.a_off + (long long)(n - 1) * lda + m <= a_elems && pr.jpvt_off >= 0 &&
                     pr.jpvt_off + n <= j_elems && pr.tau_off >= 0 && pr.tau_off + k <= t_elems &&
                     pr.b_off >= 0 && pr.b_off + (long long)l * n <= b_elems;
@@ -111,20 +115,24 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
       if (tid == 0) infos[pi] = -1;
     } else {
     float* a = apool + pr.a_off;
+    const unsigned ulda = (unsigned)lda;  // (n - 1) lda + m < 2^31: 32-bit offsets
     int* jpvt = jpool + pr.jpvt_off;
     double* tau = tpool + pr.tau_off;
     double* bout = bpool + pr.b_off;
     double* sB = S.b;
 
-    // ---- sketch B = Omega A, Omega from Philox(seed, stream pi + 1) ----
+    // ---- sketch B = Omega A on FP64 MFMA, Omega from Philox(seed, stream pi + 1) ----
+    // Each wave owns SKT 16-column tiles of B per pass; the K loop runs over A's
+    // rows in Omega chunks of RC rows generated into LDS.  Operands (16x16x4
+    // FP64): Omega(16 rows of l, 4 rows of A) from LDS, A(4 rows, 16 columns)
+    // from global memory -- a wave's load covers four consecutive rows of 16
+    // columns, so a cache line serves eight k-steps.
     double* som = reinterpret_cast<double*>(S.chunk);  // [rr * l + rho]
-    for (int cs = 0; cs < n; cs += NT) {
-      const int c = cs + tid;
-      const bool cok = c < n;
-      const float* acol = a + (long long)(cok ? c : 0) * lda;
-      double acc[LMAX];
+    const int lr16 = lane & 15, lg = lane >> 4;
+    for (int cs = 0; cs < n; cs += 16 * SKT * NW) {
+      v4d acc[SKT][2];
 #pragma unroll
-      for (int r = 0; r < LMAX; ++r) acc[r] = 0.0;
+      for (int j = 0; j < SKT; ++j) acc[j][0] = acc[j][1] = v4d{0, 0, 0, 0};
       for (int r0 = 0; r0 < m; r0 += RC) {
         // Omega(0:l, r0:r0+RC): normals q = r * l + rho, q in [r0 l, (r0 + RC) l)
         const long long q0 = (long long)r0 * l, q1 = (long long)(r0 + RC) * l;
@@ -139,20 +147,37 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
           }
         }
         __syncthreads();
-        const int rn = min(RC, m - r0);
-        // rows in groups so that their loads are in flight together
-#pragma unroll 16
-        for (int rr = 0; rr < rn; ++rr) {
-          const double av = cok ? (double)acol[r0 + rr] : 0.0;
+#pragma unroll 4
+        for (int kk = 0; kk < RC / 4; ++kk) {
+          const int kr = 4 * kk + lg;             // row of the chunk this lane feeds
+          const int krow = r0 + kr;
+          const double o0 = (lr16 < l) ? som[kr * l + (lr16 < l ? lr16 : 0)] : 0.0;
+          const double o1 = (16 + lr16 < l) ? som[kr * l + (16 + lr16 < l ? 16 + lr16 : 0)] : 0.0;
+          double bv[SKT];
 #pragma unroll
-          for (int r = 0; r < LMAX; ++r)
-            if (r < l) acc[r] += som[rr * l + r] * av;
+          for (int j = 0; j < SKT; ++j) {
+            const int col = cs + 16 * (wave + j * NW) + lr16;
+            const float x = a[(unsigned)(col < n ? col : 0) * ulda + (unsigned)(krow < m ? krow : 0)];
+            bv[j] = (col < n && krow < m) ? (double)x : 0.0;
+          }
+#pragma unroll
+          for (int j = 0; j < SKT; ++j) {
+            acc[j][0] = mfma_f64(o0, bv[j], acc[j][0]);
+            acc[j][1] = mfma_f64(o1, bv[j], acc[j][1]);
+          }
         }
       }
-      if (cok) {
+      // FP64 accumulator layout: lane l, element e holds row l/16 + 4e, column l%16
 #pragma unroll
-        for (int r = 0; r < LMAX; ++r)
-          if (r < l) sB[c * l + r] = acc[r];
+      for (int j = 0; j < SKT; ++j) {
+        const int col = cs + 16 * (wave + j * NW) + lr16;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = 16 * rt + lg + 4 * e;
+            if (col < n && r < l) sB[col * l + r] = acc[j][rt][e];
+          }
       }
     }
     for (int c = tid; c < n; c += NT) S.jp[c] = c;
@@ -377,100 +402,184 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
         if (tid == t) S.t[t * BMAX + t] = tt;
         __syncthreads();
       }
+      // M = Rhat11 R11^-1 (upper, bb x bb; zero outside): row q solves M(q, :) R11 =
+      // Rhat11(q, :), Rhat11(q, j) = B(q, i + j) the sketch's R after its QRCP
+      if (tid < BMAX) {
+        const int q = tid;
+        double mrow[BMAX];
+#pragma unroll
+        for (int j = 0; j < BMAX; ++j) {
+          double x = 0.0;
+          if (q < bb && j < bb && j >= q) {
+            x = sB[(i + j) * l + q];
+#pragma unroll
+            for (int p = 0; p < j; ++p)
+              if (p >= q) x -= mrow[p] * S.r11[p * BMAX + j];
+            x /= S.r11[j * BMAX + j];
+          }
+          mrow[j] = x;
+        }
+#pragma unroll
+        for (int j = 0; j < BMAX; ++j) S.mm[q * BMAX + j] = mrow[j];
+      }
+      __syncthreads();
 
-      // (d) trailing update of A(i:m, i+bb:n) and the sample update of B
-      float* sv = reinterpret_cast<float*>(S.chunk);  // [rr * BMAX + q]
-      const int c0 = i + bb;
-      for (int cs = c0; cs < n; cs += NT) {
-        const int c = cs + tid;
-        const bool cok = c < n;
-        float* acol = a + (long long)(cok ? c : 0) * lda;
-        float w[BMAX];
+      // (d) trailing update of A(i:m, i+bb:n) on FP32 MFMA (16x16x4) and the sample
+      // update of B.  A wave owns whole 16-column tiles: W = V^T A2 (K = the rows),
+      // W' = T^T W per column in FP64, A2 -= V W' (K = bb), then formula (1) for
+      // the tile's sketch columns from its R12 rows -- no workgroup barrier.  V is
+      // read from A itself (written back above in FP32): V(r, q) = A(r, i+q) below
+      // the unit diagonal.  Rows go in groups of TG (16-row steps); the next
+      // group's loads are issued before the current group is used, so two groups
+      // of loads are in flight per wave.
+      {
+        const int c0 = i + bb;
+        const int ntile = (n - c0 + 15) / 16;
+        const int qv = (lr16 < bb) ? lr16 : 0;
+        const unsigned vcol = (unsigned)(i + qv) * ulda;              // V(:, lane % 16)
+        unsigned vq[4];                                                // V(:, 4 kk + lane / 16)
 #pragma unroll
-        for (int q = 0; q < BMAX; ++q) w[q] = 0.0f;
-        // W(:, c) = V^T A(i:m, c)
+        for (int kk = 0; kk < 4; ++kk) vq[kk] = (unsigned)(i + (4 * kk + lg < bb ? 4 * kk + lg : 0)) * ulda;
+        for (int tt = wave; tt < ntile; tt += NW) {
+          const int col = c0 + 16 * tt + lr16;
+          const bool cok = col < n;
+          const unsigned acol = (unsigned)(cok ? col : c0) * ulda;
+          // W: lane (lg, lr16) takes rows r0 + 16u + 4 lg + e for both operands
+          v4f w4 = v4f{0, 0, 0, 0};
+          {
+            float xa0[4 * TG], xv0[4 * TG], xa1[4 * TG], xv1[4 * TG];
+            auto wload = [&](float (&xa)[4 * TG], float (&xv)[4 * TG], int r0) {
 #pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-          const int r = i + tid + NT * u;
-          __syncthreads();
+              for (int u = 0; u < TG; ++u)
 #pragma unroll
-          for (int q = 0; q < BMAX; ++q) {
-            const int d = r - i;
-            float v = (d > q) ? (float)P[u][q] : (d == q ? 1.0f : 0.0f);
-            sv[tid * BMAX + q] = (r < m && q < bb) ? v : 0.0f;
-          }
-          __syncthreads();
-          if (cok) {
-            const int rb = i + NT * u;
-            const int rn = min(NT, m - rb);
-#pragma unroll 32
-            for (int rr = 0; rr < rn; ++rr) {
-              const float av = acol[rb + rr];
+                for (int e = 0; e < 4; ++e) {
+                  const int row = r0 + 16 * u + 4 * lg + e;
+                  const unsigned rc = (unsigned)(row < m ? row : m - 1);
+                  xa[4 * u + e] = a[acol + rc];
+                  xv[4 * u + e] = a[vcol + rc];
+                }
+            };
+            auto wmma = [&](const float (&xa)[4 * TG], const float (&xv)[4 * TG], int r0) {
 #pragma unroll
-              for (int q = 0; q < BMAX; ++q) w[q] += sv[rr * BMAX + q] * av;
-            }
-          }
-        }
-        // W' = T^T W (FP64)
-        float wp[BMAX];
+              for (int u = 0; u < TG; ++u)
 #pragma unroll
-        for (int q = 0; q < BMAX; ++q) {
-          double s = 0.0;
-#pragma unroll
-          for (int j = 0; j <= q; ++j) s += S.t[j * BMAX + q] * (double)w[j];
-          wp[q] = (float)s;
-        }
-        // A(i:m, c) -= V W'; keep the new rows i..i+bb (R12) in FP64
-        double r12[BMAX];
-#pragma unroll
-        for (int q = 0; q < BMAX; ++q) r12[q] = 0.0;
-#pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-          const int r = i + tid + NT * u;
-          __syncthreads();
-#pragma unroll
-          for (int q = 0; q < BMAX; ++q) {
-            const int d = r - i;
-            float v = (d > q) ? (float)P[u][q] : (d == q ? 1.0f : 0.0f);
-            sv[tid * BMAX + q] = (r < m && q < bb) ? v : 0.0f;
-          }
-          __syncthreads();
-          if (cok) {
-            const int rb = i + NT * u;
-            const int rn = min(NT, m - rb);
-#pragma unroll 32
-            for (int rr = 0; rr < rn; ++rr) {
-              float x = acol[rb + rr];
-#pragma unroll
-              for (int q = 0; q < BMAX; ++q) x -= sv[rr * BMAX + q] * wp[q];
-              acol[rb + rr] = x;
-              if (u == 0 && rr < BMAX) {
-#pragma unroll
-                for (int q = 0; q < BMAX; ++q)
-                  if (q == rr) r12[q] = (double)x;
+                for (int e = 0; e < 4; ++e) {
+                  const int row = r0 + 16 * u + 4 * lg + e;
+                  const int d = row - i;
+                  float v = (d > lr16) ? xv[4 * u + e] : (d == lr16 ? 1.0f : 0.0f);
+                  v = (row < m && lr16 < bb) ? v : 0.0f;
+                  const float x = (row < m && cok) ? xa[4 * u + e] : 0.0f;
+                  w4 = mfma_f32(v, x, w4);
+                }
+            };
+            // the exit test comes before a group's loads, so no load is dead on a
+            // path (the compiler would sink it behind the use of the previous group)
+            int r0 = i;
+            wload(xa0, xv0, r0);
+            for (;;) {
+              if (r0 + 16 * TG >= m) {
+                wmma(xa0, xv0, r0);
+                break;
               }
+              wload(xa1, xv1, r0 + 16 * TG);
+              wmma(xa0, xv0, r0);
+              r0 += 16 * TG;
+              if (r0 + 16 * TG >= m) {
+                wmma(xa1, xv1, r0);
+                break;
+              }
+              wload(xa0, xv0, r0 + 16 * TG);
+              wmma(xa1, xv1, r0);
+              r0 += 16 * TG;
             }
           }
-        }
-        // formula (1): B(0:bb, c) -= Rhat11 R11^-1 R12(:, c)
-        if (cok && !uniform_i(S.dead)) {
-          double xs[BMAX];
+          // W' = T^T W on FP64 MFMA.  W's accumulator layout gives lane (lg, lr16)
+          // W(4 lg + e, lr16); the K index of product e is j = 4 lg + e, so the A
+          // operand is T^T(lr16, 4 lg + e) = T(4 lg + e, lr16).  The FP64 result
+          // holds W'(lg + 4 e, lr16): element kk is the B operand -W'(4 kk + lg, lr16)
+          // of the update's product kk.
+          float wq[4];
+          {
+            v4d wp = v4d{0, 0, 0, 0};
 #pragma unroll
-          for (int q = BMAX - 1; q >= 0; --q) {
-            double s = r12[q];
+            for (int e = 0; e < 4; ++e) wp = mfma_f64(S.t[(4 * lg + e) * BMAX + lr16], (double)w4[e], wp);
 #pragma unroll
-            for (int j = q + 1; j < BMAX; ++j)
-              if (j < bb) s -= S.r11[q * BMAX + j] * xs[j];
-            xs[q] = (q < bb) ? s / S.r11[q * BMAX + q] : 0.0;
+            for (int kk = 0; kk < 4; ++kk) wq[kk] = (float)(-wp[kk]);
           }
+          // A2 -= V W': C tile rows r0 + 16u + 4 lg + e, column lr16 (accumulator layout);
+          // A operand V(r0 + 16u + lr16, 4 kk + lg)
+          float r12v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+          {
+            float xc0[4 * TG], xw0[4 * TG], xc1[4 * TG], xw1[4 * TG];
+            auto uload = [&](float (&xc)[4 * TG], float (&xw)[4 * TG], int r0) {
 #pragma unroll
-          for (int q = 0; q < BMAX; ++q) {
-            if (q < bb) {
-              double s = 0.0;
+              for (int u = 0; u < TG; ++u) {
 #pragma unroll
-              for (int j = q; j < BMAX; ++j)
-                if (j < bb) s += sB[(i + j) * l + q] * xs[j];
-              sB[c * l + q] -= s;
+                for (int e = 0; e < 4; ++e) {
+                  const int row = r0 + 16 * u + 4 * lg + e;
+                  xc[4 * u + e] = a[acol + (unsigned)(row < m ? row : m - 1)];
+                }
+                const int vr = r0 + 16 * u + lr16;
+                const unsigned vrc = (unsigned)(vr < m ? vr : m - 1);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) xw[4 * u + kk] = a[vq[kk] + vrc];
+              }
+            };
+            auto ucomp = [&](const float (&xc)[4 * TG], const float (&xw)[4 * TG], int r0) {
+#pragma unroll
+              for (int u = 0; u < TG; ++u) {
+                const int rb = r0 + 16 * u;
+                v4f c = v4f{xc[4 * u], xc[4 * u + 1], xc[4 * u + 2], xc[4 * u + 3]};
+                const int vr = rb + lr16;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                  const int q = 4 * kk + lg;
+                  const int d = vr - i;
+                  float v = (d > q) ? xw[4 * u + kk] : (d == q ? 1.0f : 0.0f);
+                  v = (vr < m && q < bb) ? v : 0.0f;
+                  c = mfma_f32(v, wq[kk], c);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  const int row = rb + 4 * lg + e;
+                  if (cok && row < m) a[acol + (unsigned)row] = c[e];
+                  if (rb == i) r12v[e] = c[e];   // R12(4 lg + e, lr16)
+                }
+              }
+            };
+            // a group's loads are issued before the previous group's stores
+            int r0 = i;
+            uload(xc0, xw0, r0);
+            for (;;) {
+              if (r0 + 16 * TG >= m) {
+                ucomp(xc0, xw0, r0);
+                break;
+              }
+              uload(xc1, xw1, r0 + 16 * TG);
+              ucomp(xc0, xw0, r0);
+              r0 += 16 * TG;
+              if (r0 + 16 * TG >= m) {
+                ucomp(xc1, xw1, r0);
+                break;
+              }
+              uload(xc0, xw0, r0 + 16 * TG);
+              ucomp(xc1, xw1, r0);
+              r0 += 16 * TG;
+            }
+          }
+          // formula (1) for this tile's columns: B(0:bb, c) -= M R12(:, c) on FP64
+          // MFMA, K index 4 lg + e as for W' (lane (lg, lr16) holds R12(4 lg + e, lr16));
+          // the result holds the update of B(lg + 4 e, lr16)
+          if (!uniform_i(S.dead)) {
+            v4d bu = v4d{0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bu = mfma_f64(S.mm[lr16 * BMAX + 4 * lg + e], (double)r12v[e], bu);
+            if (cok) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int q = lg + 4 * e;
+                if (q < bb) sB[col * l + q] -= bu[e];
+              }
             }
           }
         }
@@ -516,19 +625,19 @@ int launch_batched(hipStream_t s, int variant, int batch, const rqrcp_problem* p
   int grid = ncu;  // one problem-sized LDS footprint per compute unit
   if (grid > batch) grid = batch;
   if (grid < 1) return RQ_OK;
-  if (variant == 0) {
-    auto kern = &k_rqrcp_batched<256>;
+  auto launch = [&](auto kern, int nt) -> int {
     RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), shmem, s, batch, probs, b, l, seed, apool,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), shmem, s, batch, probs, b, l, seed, apool,
                        a_elems, jpool, j_elems, tpool, t_elems, bpool, b_elems, infos, queue);
-  } else {
-    auto kern = &k_rqrcp_batched<512>;
-    RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(512), shmem, s, batch, probs, b, l, seed, apool,
-                       a_elems, jpool, j_elems, tpool, t_elems, bpool, b_elems, infos, queue);
-  }
+    return RQ_OK;
+  };
+  int rc = RQ_OK;
+  if (variant == 0)
+    rc = launch(&k_rqrcp_batched<256>, 256);
+  else
+    rc = launch(&k_rqrcp_batched<512>, 512);
+  if (rc != RQ_OK) return rc;
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }

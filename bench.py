@@ -9,9 +9,10 @@ HBM before the timed region (one copy of A per step, since the factorization
 overwrites A); the timed region is exactly `--steps` factorizations.
 
 Reported: TFLOP/s of the algorithmic RQRCP flop count (flops.py), the
-roofline position of the dominant kernel (the fused trailing update, FP64
-MFMA), measured with HIP events on the library's stream, and the CPU oracle
-timed on a bounded sample of the same workload.
+roofline position of the dominant kernel (the per-block W = V^T A2 pass of the
+left-looking trailing update, k_gemm_big on FP64 MFMA), measured with HIP
+events on the library's stream, and the CPU oracle timed on a bounded sample
+of the same workload.
 
 Unless --no-extras, the same JSON line also carries, under "extras", one
 measurement of each of the other forms on its own workload (each a few
@@ -46,8 +47,8 @@ K, B, P = 1024, 64, 8
 SEED = 2
 PEAK_FP64_MFMA = 78.6   # TFLOP/s, MI355X dense FP64 matrix
 PEAK_HBM = 8000.0       # GB/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trail_f64_c2a_traffic.txt")
-TRAIL_SRC = os.path.join(ROOT, "paper_1804_05138_amd", "csrc", "k_trail.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wpass_f64_c2a_traffic.txt")
+TRAIL_SRC = os.path.join(ROOT, "paper_1804_05138_amd", "csrc", "k_gemm_big.hip")
 
 
 def log(msg):
@@ -55,7 +56,7 @@ def log(msg):
 
 
 def traffic_from_profile():
-    """HBM bytes per trailing-update launch from the committed counter summary,
+    """HBM bytes per launch of the W pass from the committed counter summary,
     if it was taken on the current kernel source (else None)."""
     try:
         kv = {}
@@ -560,7 +561,7 @@ def main():
         "pct_fp64_mfma_peak": round(100.0 * tflops / PEAK_FP64_MFMA, 2),
         "phases_ms_per_step": {ph: round(v[0] / args.steps, 3) for ph, v in phases.items() if v[1]},
         "roofline": {
-            "kernel": "k_trail<double, 64> (fused trailing update)",
+            "kernel": "k_gemm_big<double, TA> (per-block W = V^T A2 pass, left-looking)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
             "peak": PEAK_FP64_MFMA,

@@ -51,7 +51,7 @@ EXPORTS = (
     "rqrcp_cx_workspace_size", "rqrcp_cx", "rqrcp_cur_workspace_size", "rqrcp_cur",
     "rqrcp_compress_workspace_size", "rqrcp_compress", "rqrcp_factor_noalloc",
 )
-PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other")
+PHASES = ("sketch", "qrcp", "swap", "panel", "trail", "bupdate", "other", "final")
 
 
 class Params(ctypes.Structure):

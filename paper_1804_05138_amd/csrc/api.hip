@@ -97,8 +97,17 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t omega, sketch_part, sketch_lp, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy,
-      mark, formq, est, tourn, total;
+      mark, formq, est, tourn, vall, wpall, gmat, gpart, total;
+  bool ll;             // left-looking schedule (FP64 storage)
+  long long ldv, ldwa; // leading dimensions of the dense V (m x k) and of W' (k x n)
 };
+
+// Left-looking schedule: partial sums of the per-block W pass (one more slot
+// for the correction term), and of the small Gram products V_j^T V.
+constexpr int kLLSplit = 8;
+size_t ll_split_elems(int m, int n, int k, int b) {
+  return (size_t)b * std::max({(size_t)8 * m, (size_t)16 * n, (size_t)64 * k});
+}
 
 size_t elem_size(int t) { return t == RQRCP_F32 ? sizeof(float) : sizeof(double); }
 
@@ -154,8 +163,16 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   L.pscr = PSCR_OFF;
   L.ppart = take(panel_partial_doubles(m, std::min(b, k)) * sizeof(double));
   L.tmat = take((size_t)MAX_B * MAX_B * sizeof(double));
-  L.wpart = take(wpart_doubles(m, n, k, b) * es);
+  L.ll = prm.a_type == RQRCP_F64;
+  L.ldv = m + (m & 1);
+  L.ldwa = k + (k & 1);
+  L.wpart = take(std::max(wpart_doubles(m, n, k, b),
+                          L.ll ? (size_t)(kLLSplit + 1) * n * b : (size_t)0) * es);
   L.wp = take((size_t)b * n * sizeof(double));
+  L.vall = take(L.ll ? (size_t)L.ldv * k * sizeof(double) : 0);
+  L.wpall = take(L.ll ? (size_t)L.ldwa * n * sizeof(double) : 0);
+  L.gmat = take(L.ll ? (size_t)b * k * sizeof(double) : 0);
+  L.gpart = take(L.ll ? ll_split_elems(m, n, k, b) * sizeof(double) : 0);
   L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * es : 0);
   L.mark = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)n * sizeof(int) : 0);
   L.formq = take(form_q_work_elems(m, k, b) * es);
@@ -232,6 +249,21 @@ __global__ void k_perm_check(int n, const int* __restrict__ perm, int* __restric
 }
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
+
+// Dense copy of the reflectors of columns c .. c+w-1 over all m rows:
+// v(r, c + q) = A(r, c + q) below row c + q, 1 on it, 0 above (the unit lower
+// trapezoidal V of Alg. 2's block, kept for the left-looking products).
+template <typename T>
+__global__ void k_copy_v(int m, int c, int w, const T* __restrict__ a, long long lda,
+                         double* __restrict__ v, long long ldv) {
+  const long long total = (long long)m * w;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(e / m), r = (int)(e % m);
+    const int d = r - (c + q);
+    v[(long long)(c + q) * ldv + r] = d > 0 ? (double)a[(long long)(c + q) * lda + r] : (d == 0 ? 1.0 : 0.0);
+  }
+}
 
 // *out = ||B(0:l, c0:n)||_F^2 (one workgroup, fixed summation order).
 __global__ __launch_bounds__(1024) void k_sketch_fro2(const double* __restrict__ b, long long ldb,
@@ -310,6 +342,61 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   double* wp = (double*)(w + L.wp);
   const long long ldw = b;
   int rc;
+  // Left-looking schedule (FP64): A2 is not written per block.  Each block
+  // keeps its reflectors in the dense V (m x k) and its W' rows in W' (k x n);
+  // the rows R12 are finished in place by the sample-update kernel, a panel
+  // takes the pending update of all earlier blocks before it is factored, the
+  // per-block product W_j = V_j^T A2 reads the original A2 and subtracts
+  // (V_j^T V_<j) W'_<j, and A2 -= V W' runs once at the end.
+  const bool ll = L.ll;
+  double* vall = (double*)(w + L.vall);
+  double* wpall = (double*)(w + L.wpall);
+  double* gmat = (double*)(w + L.gmat);
+  double* gpart = (double*)(w + L.gpart);
+  const long long ldv = L.ldv, ldwa = L.ldwa;
+  const size_t gpart_elems = ll ? ll_split_elems(m, n, k, b) : 0;
+  auto copy_v = [&](int c, int wd) -> int {
+    hipLaunchKernelGGL(k_copy_v<T>, dim3(grid_for((long long)m * wd)), dim3(256), 0, s, m, c, wd,
+                       (const T*)A, (long long)lda, vall, ldv);
+    RQ_HIP_CHECK(hipGetLastError());
+    return 0;
+  };
+  // W partials of block (c, wd) over the trailing columns c+wd .. n: the read
+  // pass V^T A2 (split over rows) and, after the first block, the correction
+  // -(V^T V_<c) W'(0:c, .) as one more partial.  *nsp_out = partials written.
+  auto w_pass = [&](int c, int wd, int* nsp_out) -> int {
+    const int cb = c + wd, nc = n - cb;
+    *nsp_out = 0;
+    if (nc <= 0) return 0;
+    const int tiles = (nc + 255) / 256;
+    int sp = (512 + tiles - 1) / tiles;
+    sp = std::max(1, std::min(sp, std::min(kLLSplit, (m - c) / 256)));
+    int got = 0;
+    int r;
+    {
+      PhaseTimer pt(h, RQRCP_PHASE_TRAIL, 2.0 * (m - c) * (double)wd * nc,
+                    8.0 * (m - c) * (double)nc);
+      r = gemm_big_partials<double>(s, true, wd, nc, m - c, vall + c + (long long)c * ldv, ldv,
+                                    (const double*)A + c + (long long)cb * lda, lda,
+                                    (double*)wpart, sp, &got);
+      if (r) return r;
+    }
+    if (c > 0) {
+      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)c * ((m - c) + nc),
+                    8.0 * (double)c * ((m - c) + nc));
+      // G = V_c^T V(:, 0:c) over rows c .. m (V_c vanishes above row c)
+      r = gemm_big<double>(s, true, wd, c, m - c, 1.0, vall + c + (long long)c * ldv, ldv,
+                           vall + c, ldv, 0.0, gmat, wd, gpart, gpart_elems);
+      if (r) return r;
+      r = gemm_big<double>(s, false, wd, nc, c, -1.0, gmat, wd, wpall + (long long)cb * ldwa,
+                           ldwa, 0.0, (double*)wpart + (long long)got * nc * wd, wd, gpart,
+                           gpart_elems);
+      if (r) return r;
+      ++got;
+    }
+    *nsp_out = got;
+    return 0;
+  };
 
   hipLaunchKernelGGL(k_init, dim3(grid_for(n)), dim3(256), 0, s, qscr, pscr, info, jpvt, n,
                      frozen ? 0 : 1, cand, frozen ? 0LL : (long long)qrcp_cand_doubles(l, n));
@@ -381,22 +468,36 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m, bb, 0), 16.0 * m * (double)bb);
     rc = launch_panel<T>(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart, stepwise);
     if (rc) return rc;
+    if (ll && (rc = copy_v(0, bb))) return rc;
   }
   if (n - bb > 0) {
-    PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(0, 0, bb, n - bb), 8.0 * m * (double)(n - bb));
-    TrailPlan pl = trail_plan(m, n - bb, trail_strip<T>(bb));
-    rc = launch_trail<T>(s, m, A, lda, 0, 0, bb, (const double*)nullptr, 0, 0, bb, n, wpart,
-                         pl.nsplit, &nsp);
+    if (ll) {
+      rc = w_pass(0, bb, &nsp);
+    } else {
+      PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(0, 0, bb, n - bb),
+                    8.0 * m * (double)(n - bb));
+      TrailPlan pl = trail_plan(m, n - bb, trail_strip<T>(bb));
+      rc = launch_trail<T>(s, m, A, lda, 0, 0, bb, (const double*)nullptr, 0, 0, bb, n, wpart,
+                           pl.nsplit, &nsp);
+    }
     if (rc) return rc;
   }
   for (;;) {
     const int c0 = i + bb;
     const int ncols = n - c0;
     if (ncols > 0) {
-      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * bb * (double)bb * ncols,
+      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * bb * (double)bb * ncols + 2.0 * bb * (double)i * ncols,
                     8.0 * ncols * (double)bb * (nsp + 4));
-      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, wpart, nsp, wp, ldw, frozen ? nullptr : B,
-                          ldb, c0, ncols, info);
+      if (ll && i > 0) {
+        // rows i..i+bb of the trailing columns take the updates of the earlier blocks
+        rc = gemm_big<double>(s, false, bb, ncols, i, -1.0, vall + i, ldv,
+                              wpall + (long long)c0 * ldwa, ldwa, 1.0,
+                              (double*)A + i + (long long)c0 * lda, lda, gpart, gpart_elems);
+        if (rc) return rc;
+      }
+      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, wpart, nsp,
+                             ll ? wpall + (long long)c0 * ldwa + i : wp, ll ? ldwa : ldw,
+                             frozen ? nullptr : B, ldb, c0, ncols, info, ll ? A : (T*)nullptr);
       if (rc) return rc;
     }
     bool stop = false;
@@ -416,11 +517,28 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
           if (rc) return rc;
         }
         PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
-        rc = launch_apply_pairs<T>(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs,
-                                   &qscr->npairs, 2 * bbn);
+        if (ll)
+          rc = launch_apply_pairs<T>(s, m, A, lda, c0, jpvt, wpall + (long long)c0 * ldwa, c0,
+                                     ldwa, 0, pairs, &qscr->npairs, 2 * bbn);
+        else
+          rc = launch_apply_pairs<T>(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs,
+                                     &qscr->npairs, 2 * bbn);
         if (rc) return rc;
       }
-      {
+      if (ll) {
+        PhaseTimer pt(h, RQRCP_PHASE_PANEL,
+                      panel_flops(m - c0, bbn, 0) + 2.0 * (m - c0) * (double)c0 * bbn,
+                      16.0 * (m - c0) * (double)bbn);
+        // the panel's pending update from all earlier blocks, then its QR
+        rc = gemm_big<double>(s, false, m - c0, bbn, c0, -1.0, vall + c0, ldv,
+                              wpall + (long long)c0 * ldwa, ldwa, 1.0,
+                              (double*)A + c0 + (long long)c0 * lda, lda, gpart, gpart_elems);
+        if (rc) return rc;
+        rc = launch_panel<T>(s, m, A, lda, c0, bbn, 0, nullptr, 0, tau, tmat, pscr, ppart,
+                             stepwise);
+        if (rc) return rc;
+        if ((rc = copy_v(c0, bbn))) return rc;
+      } else {
         PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m - c0, bbn, bb),
                       16.0 * (m - i) * (double)bbn);
         rc = launch_panel<T>(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart,
@@ -429,11 +547,15 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       }
       const int nrest = n - (c0 + bbn);
       if (nrest > 0) {
-        PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, bbn, nrest),
-                      16.0 * (m - i) * (double)nrest);
-        TrailPlan pl = trail_plan(m - i, nrest, trail_strip<T>(std::max(bb, bbn)));
-        rc = launch_trail<T>(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw, c0 + bbn,
-                              c0 + bbn, n, wpart, pl.nsplit, &nsp);
+        if (ll) {
+          rc = w_pass(c0, bbn, &nsp);
+        } else {
+          PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, bbn, nrest),
+                        16.0 * (m - i) * (double)nrest);
+          TrailPlan pl = trail_plan(m - i, nrest, trail_strip<T>(std::max(bb, bbn)));
+          rc = launch_trail<T>(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw,
+                               c0 + bbn, c0 + bbn, n, wpart, pl.nsplit, &nsp);
+        }
         if (rc) return rc;
       } else {
         nsp = 0;
@@ -441,7 +563,15 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       i = c0;
       bb = bbn;
     } else {
-      if (ncols > 0) {
+      if (ncols > 0 && ll) {
+        // A2 -= V W' for all blocks at once (rows 0..c0 are final already)
+        PhaseTimer pt(h, RQRCP_PHASE_FINAL, 2.0 * (m - c0) * (double)c0 * ncols,
+                      16.0 * (m - c0) * (double)ncols);
+        rc = gemm_big<double>(s, false, m - c0, ncols, c0, -1.0, vall + c0, ldv,
+                              wpall + (long long)c0 * ldwa, ldwa, 1.0,
+                              (double*)A + c0 + (long long)c0 * lda, lda);
+        if (rc) return rc;
+      } else if (ncols > 0) {
         PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, 0, ncols),
                       16.0 * (m - i) * (double)ncols);
         int dummy = 0;

@@ -15,6 +15,19 @@ int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, T alpha, const T*
 
 size_t splitk_elems(int m, int n);
 
+// Large-tile GEMM (k_gemm_big.hip): C = alpha op(A) B + beta C, column-major,
+// op(A) = A^T when ta.  With ws (ws_elems elements), a shape with few output
+// tiles and a long K is split over K, partial sums in ws added in order.
+template <typename T>
+int gemm_big(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A, long long lda,
+             const T* B, long long ldb, T beta, T* C, long long ldc, T* ws = nullptr,
+             size_t ws_elems = 0);
+// The raw sums op(A) B of at most max_split K ranges (whole 16-steps) into
+// part[z][N][M] (leading dimension M); *nsplit_out = ranges written.
+template <typename T>
+int gemm_big_partials(hipStream_t s, bool ta, int M, int N, int K, const T* A, long long lda,
+                      const T* B, long long ldb, T* part, int max_split, int* nsplit_out);
+
 // Dense V (rows x bb), Gram V^T V and T of one reflector block.
 template <typename T>
 int block_t(hipStream_t s, int rows, int bb, const T* a, long long lda, const double* tau, T* vd,

@@ -30,12 +30,13 @@ constexpr int SP = CW + 1;    // LDS row pitch of the column tiles
 constexpr int AP = SB + 1;    // LDS pitch of the bb x bb blocks
 
 template <typename T>
-__global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* __restrict__ a, long long lda,
+__global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long lda,
                                                   int i, int bb, const double* __restrict__ tm,
                                                   const T* __restrict__ wpart, int nsplit,
                                                   double* __restrict__ wp, long long ldw,
                                                   double* __restrict__ bsk, long long ldb,
-                                                  int c0, int ncols, const int* __restrict__ info) {
+                                                  int c0, int ncols, const int* __restrict__ info,
+                                                  T* r12out) {
   extern __shared__ double smem[];
   double* sT = smem;                 // T(q, r) at sT[r * AP + q]; later Rhat11(q, r)
   double* sA = sT + SB * AP;         // A(i + r, i + c) at sA[c * AP + r]
@@ -129,7 +130,9 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* __restrict__ a
     const int c = e / bb, r = e % bb;
     wp[(long long)(cb + c) * ldw + r] = sX[r * SP + c];
   }
-  if (bsk == nullptr || *info != 0) return;
+  // uniform: the sample update runs (sketch given, pivoting not stopped)
+  const bool sample = upd && *info == 0;
+  if (!sample && r12out == nullptr) return;
   // Rhat11 = triu(B(0:bb, i:i+bb)) into sT; R12 starts as A(i:i+bb, col)
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
@@ -153,6 +156,14 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* __restrict__ a
       sW[r * SP + c] = sW[r * SP + c] - sX[r * SP + c] - acc[t][e];
     }
   __syncthreads();
+  // the final rows R12 = A(i:i+bb, col) (left-looking schedule: A2 itself is
+  // not updated until the end)
+  if (r12out != nullptr)
+    for (int e = tid; e < nc * bb; e += BT) {
+      const int c = e / bb, r = e % bb;
+      r12out[(long long)(c0 + cb + c) * lda + i + r] = (T)sW[r * SP + c];
+    }
+  if (!sample) return;
   // X = R11^{-1} R12: back substitution, column `lane` in registers of wave 0
   if (wave == 0) {
     double y[SB];
@@ -200,12 +211,13 @@ constexpr int QP = QW + 1;     // LDS row pitch of the column tiles
 constexpr int QAP = QB + 1;    // LDS pitch of a quadrant
 
 template <typename T>
-__global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* __restrict__ a, long long lda,
+__global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* a, long long lda,
                                                   int i, int bb, const double* __restrict__ tm,
                                                   const T* __restrict__ wpart, int nsplit,
                                                   double* __restrict__ wp, long long ldw,
                                                   double* __restrict__ bsk, long long ldb,
-                                                  int c0, int ncols, const int* __restrict__ info) {
+                                                  int c0, int ncols, const int* __restrict__ info,
+                                                  T* r12out) {
   extern __shared__ double smem[];
   double* sQ = smem;                 // quadrant: element (row r, column k) at sQ[k * QAP + r]
   double* sQ2 = sQ + QB * QAP;       // second quadrant, same layout
@@ -310,7 +322,8 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* __restrict__ a
     const int c = e / bb, r = e % bb;
     wp[(long long)(cb + c) * ldw + r] = sX[r * QP + c];
   }
-  if (bsk == nullptr || *info != 0) return;
+  const bool sample = bsk != nullptr && *info == 0;  // uniform
+  if (!sample && r12out == nullptr) return;
 
   // R12 = A(i:i+bb, col) - V11 W'  (V11 unit lower: A(i + r, i + q), q < r)
   auto aget = [&](int r, int k) { return (double)a[(long long)(i + k) * lda + i + r]; };
@@ -357,6 +370,12 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* __restrict__ a
       sW[r * QP + c] = sW[r * QP + c] - sX[r * QP + c] - acc[t][e];
     }
   __syncthreads();
+  if (r12out != nullptr)
+    for (int e = tid; e < nc * bb; e += BT) {
+      const int c = e / bb, r = e % bb;
+      r12out[(long long)(c0 + cb + c) * lda + i + r] = (T)sW[r * QP + c];
+    }
+  if (!sample) return;
 
   // 64-row back substitution of the rows h*64.. against the quadrant in sQ
   // (R11(64h + q, 64h + r) at sQ[r * QAP + q]), column `lane` in registers.
@@ -438,7 +457,7 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* __restrict__ a
 template <typename T>
 int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int bb,
                    const double* t, const T* wpart, int nsplit, double* wp, long long ldw,
-                   double* bsk, long long ldb, int c0, int ncols, const int* info) {
+                   double* bsk, long long ldb, int c0, int ncols, const int* info, T* r12out) {
   if (ncols <= 0) return RQ_OK;
   if (bb > MAX_B) return RQ_ERR_LIMIT;
   if (bb <= SB) {
@@ -446,7 +465,7 @@ int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int b
     RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bupdate_s<T>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
     hipLaunchKernelGGL(k_bupdate_s<T>, dim3((ncols + CW - 1) / CW), dim3(BT), shmem, s, m, a, lda,
-                       i, bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info);
+                       i, bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info, r12out);
     RQ_HIP_CHECK(hipGetLastError());
     return RQ_OK;
   }
@@ -455,15 +474,15 @@ int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int b
   RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bupdate_q<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(k_bupdate_q<T>, dim3((ncols + QW - 1) / QW), dim3(BT), shmem, s, m, a, lda, i,
-                     bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info);
+                     bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info, r12out);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
 template int launch_bupdate<double>(hipStream_t, int, const double*, long long, int, int,
                                     const double*, const double*, int, double*, long long,
-                                    double*, long long, int, int, const int*);
+                                    double*, long long, int, int, const int*, double*);
 template int launch_bupdate<float>(hipStream_t, int, const float*, long long, int, int,
                                    const double*, const float*, int, double*, long long, double*,
-                                   long long, int, int, const int*);
+                                   long long, int, int, const int*, float*);
 
 }  // namespace rq

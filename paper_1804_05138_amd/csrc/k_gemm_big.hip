@@ -1,0 +1,321 @@
+// Large-tile GEMM on MFMA for the left-looking trailing update:
+//     C = alpha op(A) B + beta C     (column-major, op(A) = A or A^T),
+// or, for a split reduction, the raw partial sums of K ranges.
+//
+// Each wave owns a 64 x 64 block of C (4 x 4 MFMA tiles of 16 x 16, FP64
+// v_mfma_f64_16x16x4f64 or FP32 v_mfma_f32_16x16x4f32); a workgroup of WM x WN
+// waves covers a (64 WM) x (64 WN) tile.  K advances in steps of BK through two
+// LDS buffers: the global loads of step t+1 are in registers while step t runs
+// on the matrix cores, one barrier per step.  With 64 x 64 per wave every LDS
+// operand read feeds four MFMAs, twice the reuse of the 32 x 32 wave blocks of
+// the generic GEMM (k_gemm.hip).
+//
+// Loads move two consecutive elements of the contiguous index per lane
+// (8- or 16-byte vector loads) when leading dimensions, bases and the
+// contiguous extents allow it; otherwise one element.  Out-of-range elements
+// are read from clamped (always valid) addresses and masked to zero.
+//
+// Tile order: consecutive workgroups go to different XCDs (the dispatcher
+// deals them round-robin over the eight dies), so the linear index is
+// remapped to give each die a contiguous range of tiles, walked in groups of
+// eight tile rows, so the operand panels a die's workgroups share stay in its
+// own L2.
+#include <algorithm>
+
+#include "internal.h"
+#include "gemm.h"
+
+namespace rq {
+namespace {
+
+template <typename T>
+struct BigMfma;
+template <>
+struct BigMfma<double> {
+  typedef v4d acc_t;
+  static RQ_DEV acc_t run(double a, double b, acc_t c) { return mfma_f64(a, b, c); }
+};
+template <>
+struct BigMfma<float> {
+  typedef v4f acc_t;
+  static RQ_DEV acc_t run(float a, float b, acc_t c) { return mfma_f32(a, b, c); }
+};
+
+constexpr int kPad = 1;  // LDS row padding (elements)
+
+template <typename T, bool TA, int WM, int WN, int BK, int OCC, bool VEC>
+__global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
+    int M, int N, int K, T alpha, const T* __restrict__ A, long long lda, const T* __restrict__ B,
+    long long ldb, T beta, T* __restrict__ C, long long ldc, int kchunk, T* __restrict__ part) {
+  typedef typename BigMfma<T>::acc_t acc_t;
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  constexpr int NT = 64 * WM * WN, BM = 64 * WM, BN = 64 * WN;
+  constexpr int VW = VEC ? 2 : 1;
+  constexpr int NLA = BM * BK / NT / VW, NLB = BN * BK / NT / VW;
+  static_assert(NLA * NT * VW == BM * BK && NLB * NT * VW == BN * BK, "tiles split evenly");
+  __shared__ T sA[2][BK][BM + kPad];
+  __shared__ T sB[2][BK][BN + kPad];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr16 = lane & 15, lg = lane >> 4;
+
+  const int nbm = (M + BM - 1) / BM, nbn = (N + BN - 1) / BN, tiles = nbm * nbn;
+  int tile = blockIdx.x;
+  if ((tiles & 7) == 0) tile = (tile & 7) * (tiles >> 3) + (tile >> 3);
+  constexpr int GM = 8;
+  const int first = tile / (GM * nbn) * GM, gsz = min(nbm - first, GM);
+  const int tm = first + (tile % (GM * nbn)) % gsz, tn = (tile % (GM * nbn)) / gsz;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int wm = (wave % WM) * 64, wn = (wave / WM) * 64;
+  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+
+  acc_t acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
+
+  T ra[NLA * VW], rb[NLB * VW];
+  // element (ci, oi) of a load: ci along the contiguous index (VW at a time)
+  auto ld2 = [&](const T* p, bool ok0, bool ok1, T* dst) {
+    if constexpr (VEC) {
+      const T2 v = *reinterpret_cast<const T2*>(p);
+      dst[0] = ok0 ? v.x : T(0);
+      dst[1] = ok1 ? v.y : T(0);
+    } else {
+      const T v = *p;
+      dst[0] = ok0 ? v : T(0);
+    }
+  };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < NLA; ++j) {
+      const int u = tid + NT * j;
+      if constexpr (!TA) {  // A(m, k) at A[k lda + m]: contiguous along m
+        const int mi = (u % (BM / VW)) * VW, ki = u / (BM / VW);
+        const int gm = m0 + mi, gk = k0 + ki;
+        const int gmc = gm < M ? gm : ((M - 1) & ~(VW - 1)), gkc = gk < ke ? gk : ke - 1;
+        ld2(A + (long long)gkc * lda + gmc, gm < M && gk < ke, gm + 1 < M && gk < ke, ra + VW * j);
+      } else {              // op(A)(m, k) = A[m lda + k]: contiguous along k
+        const int ki = (u % (BK / VW)) * VW, mi = u / (BK / VW);
+        const int gm = m0 + mi, gk = k0 + ki;
+        const int gmc = gm < M ? gm : M - 1, gkc = gk < ke ? gk : ke - VW;
+        ld2(A + (long long)gmc * lda + gkc, gm < M && gk < ke, gm < M && gk + 1 < ke, ra + VW * j);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NLB; ++j) {
+      const int u = tid + NT * j;
+      const int ki = (u % (BK / VW)) * VW, ni = u / (BK / VW);
+      const int gn = n0 + ni, gk = k0 + ki;
+      const int gnc = gn < N ? gn : N - 1, gkc = gk < ke ? gk : ke - VW;
+      ld2(B + (long long)gnc * ldb + gkc, gn < N && gk < ke, gn < N && gk + 1 < ke, rb + VW * j);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NLA; ++j) {
+      const int u = tid + NT * j;
+      if constexpr (!TA) {
+        const int mi = (u % (BM / VW)) * VW, ki = u / (BM / VW);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) sA[buf][ki][mi + v] = ra[VW * j + v];
+      } else {
+        const int ki = (u % (BK / VW)) * VW, mi = u / (BK / VW);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) sA[buf][ki + v][mi] = ra[VW * j + v];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NLB; ++j) {
+      const int u = tid + NT * j;
+      const int ki = (u % (BK / VW)) * VW, ni = u / (BK / VW);
+#pragma unroll
+      for (int v = 0; v < VW; ++v) sB[buf][ki + v][ni] = rb[VW * j + v];
+    }
+  };
+
+  if (kb < ke) {
+    load(kb);
+    stash(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) load(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) av[x] = sA[buf][4 * ks + lg][wm + 16 * x + lr16];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) bv[y] = sB[buf][4 * ks + lg][wn + 16 * y + lr16];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = BigMfma<T>::run(av[x], bv[y], acc[x][y]);
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wm + 16 * x + acc_row<T>(lg, e);
+        const int gn = n0 + wn + 16 * y + lr16;
+        if (gm < M && gn < N) {
+          if (part) {
+            part[((size_t)blockIdx.y * N + gn) * M + gm] = acc[x][y][e];
+          } else {
+            T* c = C + (long long)gn * ldc + gm;
+            const T v = alpha * acc[x][y][e];
+            *c = (beta == T(0)) ? v : v + beta * (*c);
+          }
+        }
+      }
+}
+
+template <typename T, bool TA, int WM, int WN, int BK, int OCC>
+void launch_big(hipStream_t s, bool vec, int M, int N, int K, T alpha, const T* A, long long lda,
+                const T* B, long long ldb, T beta, T* C, long long ldc, int kchunk, int nsplit,
+                T* part) {
+  const int tiles = ((M + 64 * WM - 1) / (64 * WM)) * ((N + 64 * WN - 1) / (64 * WN));
+  const dim3 grid(tiles, nsplit), block(64 * WM * WN);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, BK, OCC, true>), grid, block, 0, s, M, N, K,
+                       alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+  else
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, BK, OCC, false>), grid, block, 0, s, M, N, K,
+                       alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+}
+
+// C = alpha sum_z part[z] + beta C (partials in split order)
+template <typename T>
+__global__ void k_big_sum(int M, int N, int S, const T* __restrict__ part, T alpha, T beta,
+                          T* __restrict__ C, long long ldc) {
+  const long long total = (long long)M * N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    T acc = part[e];
+    for (int z = 1; z < S; ++z) acc += part[(size_t)z * total + e];
+    T* c = C + (e / M) * ldc + e % M;
+    const T v = alpha * acc;
+    *c = (beta == T(0)) ? v : v + beta * (*c);
+  }
+}
+
+constexpr int kBK = 16;
+
+unsigned grid_for(long long total) {
+  const long long g = (total + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+// Output tiles of the variant gemm_big picks for this shape.
+int big_tiles(bool ta, int M, int N) {
+  int bm = 128, bn = 128;
+  if (ta && M <= 64) { bm = 64; bn = 256; }
+  else if (!ta && M <= 64) { bm = 64; bn = 128; }
+  else if (!ta && N <= 64) { bm = 128; bn = 64; }
+  return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+}
+
+template <typename T>
+void big_launch(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A, long long lda,
+                const T* B, long long ldb, T beta, T* C, long long ldc, int kchunk, int nsplit,
+                T* part) {
+  // two-element loads: even leading dimensions and K, aligned bases, and an
+  // even row count when A's rows are the contiguous index
+  const uintptr_t al = 2 * sizeof(T);
+  const bool vec = K > 0 && lda % 2 == 0 && ldb % 2 == 0 && K % 2 == 0 && kchunk % 2 == 0 &&
+                   (reinterpret_cast<uintptr_t>(A) % al) == 0 &&
+                   (reinterpret_cast<uintptr_t>(B) % al) == 0 && (ta || M % 2 == 0);
+  if (ta) {
+    if (M <= 64)
+      launch_big<T, true, 1, 4, 8, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                      kchunk, nsplit, part);
+    else
+      launch_big<T, true, 2, 2, kBK, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                        kchunk, nsplit, part);
+  } else {
+    if (M <= 64)
+      launch_big<T, false, 1, 2, kBK, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                         kchunk, nsplit, part);
+    else if (N <= 64)
+      launch_big<T, false, 2, 1, kBK, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                         kchunk, nsplit, part);
+    else
+      launch_big<T, false, 2, 2, kBK, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                         kchunk, nsplit, part);
+  }
+}
+
+// K ranges of whole 16-steps for at most `want` splits: (kchunk, count)
+void big_split(int K, int want, int* kchunk, int* nsplit) {
+  if (want < 2 || K <= kBK) {
+    *kchunk = K > 0 ? K : 1;
+    *nsplit = 1;
+    return;
+  }
+  *kchunk = ((K + want - 1) / want + kBK - 1) / kBK * kBK;
+  *nsplit = (K + *kchunk - 1) / *kchunk;
+}
+
+}  // namespace
+
+template <typename T>
+int gemm_big(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A, long long lda,
+             const T* B, long long ldb, T beta, T* C, long long ldc, T* ws, size_t ws_elems) {
+  if (M <= 0 || N <= 0) return RQ_OK;
+  // few output tiles and a long reduction: split K so the grid covers the
+  // chip (1024 workgroups), raw partials in ws, summed in split order
+  int want = 1;
+  const int tiles = big_tiles(ta, M, N);
+  if (ws && tiles < 512 && K >= 4 * kBK) {
+    want = (1024 + tiles - 1) / tiles;
+    want = std::min(want, K / (2 * kBK));
+    want = std::min<long long>(want, (long long)(ws_elems / ((size_t)M * N)));
+    want = std::min(want, 64);
+  }
+  int kchunk = 1, nsplit = 1;
+  big_split(K, want, &kchunk, &nsplit);
+  if (nsplit > 1) {
+    big_launch<T>(s, ta, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, 0, kchunk, nsplit, ws);
+    hipLaunchKernelGGL(k_big_sum<T>, dim3(grid_for((long long)M * N)), dim3(256), 0, s, M, N,
+                       nsplit, (const T*)ws, alpha, beta, C, ldc);
+  } else {
+    big_launch<T>(s, ta, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, nullptr);
+  }
+  RQ_HIP_CHECK(hipGetLastError());
+  return RQ_OK;
+}
+
+template <typename T>
+int gemm_big_partials(hipStream_t s, bool ta, int M, int N, int K, const T* A, long long lda,
+                      const T* B, long long ldb, T* part, int max_split, int* nsplit_out) {
+  *nsplit_out = 0;
+  if (M <= 0 || N <= 0) return RQ_OK;
+  int kchunk = 1, nsplit = 1;
+  big_split(K, max_split, &kchunk, &nsplit);
+  big_launch<T>(s, ta, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, 0, kchunk, nsplit, part);
+  RQ_HIP_CHECK(hipGetLastError());
+  *nsplit_out = nsplit;
+  return RQ_OK;
+}
+
+template int gemm_big<double>(hipStream_t, bool, int, int, int, double, const double*, long long,
+                              const double*, long long, double, double*, long long, double*,
+                              size_t);
+template int gemm_big<float>(hipStream_t, bool, int, int, int, float, const float*, long long,
+                             const float*, long long, float, float*, long long, float*, size_t);
+template int gemm_big_partials<double>(hipStream_t, bool, int, int, int, const double*, long long,
+                                       const double*, long long, double*, int, int*);
+template int gemm_big_partials<float>(hipStream_t, bool, int, int, int, const float*, long long,
+                                      const float*, long long, float*, int, int*);
+
+}  // namespace rq

@@ -250,6 +250,17 @@ __global__ void k_perm_check(int n, const int* __restrict__ perm, int* __restric
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
+// out[e] = sum_z p[z stride + e], e < count (partials added in order)
+__global__ void k_sum_parts(long long count, int nparts, long long stride,
+                            const double* __restrict__ p, double* __restrict__ out) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x) {
+    double acc = p[e];
+    for (int z = 1; z < nparts; ++z) acc += p[(long long)z * stride + e];
+    out[e] = acc;
+  }
+}
+
 // Dense copy of the reflectors of columns c .. c+w-1 over all m rows:
 // v(r, c + q) = A(r, c + q) below row c + q, 1 on it, 0 above (the unit lower
 // trapezoidal V of Alg. 2's block, kept for the left-looking products).
@@ -363,34 +374,69 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   };
   // W partials of block (c, wd) over the trailing columns c+wd .. n: the read
   // pass V^T A2 (split over rows) and, after the first block, the correction
-  // -(V^T V_<c) W'(0:c, .) as one more partial.  *nsp_out = partials written.
+  // -(V^T V_<c) W'(0:c, .) as one more partial.  *nsp_out = partials written;
+  // partial z of W starts at wpw + z pstr wd (pstr = 0: n - c - wd columns).
+  double* wpw = (double*)wpart;
+  long long pstr = 0;
   auto w_pass = [&](int c, int wd, int* nsp_out) -> int {
     const int cb = c + wd, nc = n - cb;
     *nsp_out = 0;
+    wpw = (double*)wpart;
+    pstr = 0;
     if (nc <= 0) return 0;
-    const int tiles = (nc + 255) / 256;
-    int sp = (512 + tiles - 1) / tiles;
-    sp = std::max(1, std::min(sp, std::min(kLLSplit, (m - c) / 256)));
-    int got = 0;
-    int r;
+    double* part = (double*)wpart;
+    const double* vc = vall + c + (long long)c * ldv;  // V_c, rows c .. m
+    int got = 0, r = 0;
+    // one pass over [V(c:m, 0:c) | A(c:m, cb:n)]: the Gram block G = V_c^T V_<c
+    // rides along with W = V_c^T A2
+    const int nt = c + nc;
     {
+      const int tiles = (nt + 255) / 256;
+      int sp = (1024 + tiles - 1) / tiles;
+      sp = std::max(1, std::min(sp, std::min(kLLSplit, (m - c) / 256)));
+      PhaseTimer pt(h, RQRCP_PHASE_TRAIL, 2.0 * (m - c) * (double)wd * nt,
+                    8.0 * (m - c) * (double)nt);
+      r = wpass_partials(s, m - c, wd, nt, c, vc, ldv, vall + c, ldv,
+                         (const double*)A + c + (long long)cb * lda, lda, part, sp, &got);
+      if (r && r != RQ_ERR_LIMIT) return r;
+    }
+    if (r == 0) {
+      wpw = part + (long long)c * wd;
+      pstr = nt;
+      if (c > 0) {
+        PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)c * nc, 8.0 * (double)c * nc);
+        hipLaunchKernelGGL(k_sum_parts, dim3(grid_for((long long)c * wd)), dim3(256), 0, s,
+                           (long long)c * wd, got, (long long)nt * wd, (const double*)part, gmat);
+        RQ_HIP_CHECK(hipGetLastError());
+        r = gemm_big<double>(s, false, wd, nc, c, -1.0, gmat, wd, wpall + (long long)cb * ldwa,
+                             ldwa, 0.0, part + ((long long)got * nt + c) * wd, wd, gpart,
+                             gpart_elems);
+        if (r) return r;
+        ++got;
+      }
+      *nsp_out = got;
+      return 0;
+    }
+    // shapes the streaming pass does not take (odd sizes): the general GEMM
+    {
+      const int tiles = (nc + 255) / 256;
+      int sp = (512 + tiles - 1) / tiles;
+      sp = std::max(1, std::min(sp, std::min(kLLSplit, (m - c) / 256)));
       PhaseTimer pt(h, RQRCP_PHASE_TRAIL, 2.0 * (m - c) * (double)wd * nc,
                     8.0 * (m - c) * (double)nc);
-      r = gemm_big_partials<double>(s, true, wd, nc, m - c, vall + c + (long long)c * ldv, ldv,
-                                    (const double*)A + c + (long long)cb * lda, lda,
-                                    (double*)wpart, sp, &got);
+      r = gemm_big_partials<double>(s, true, wd, nc, m - c, vc, ldv,
+                                    (const double*)A + c + (long long)cb * lda, lda, part, sp,
+                                    &got);
       if (r) return r;
     }
     if (c > 0) {
       PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)c * ((m - c) + nc),
                     8.0 * (double)c * ((m - c) + nc));
-      // G = V_c^T V(:, 0:c) over rows c .. m (V_c vanishes above row c)
-      r = gemm_big<double>(s, true, wd, c, m - c, 1.0, vall + c + (long long)c * ldv, ldv,
-                           vall + c, ldv, 0.0, gmat, wd, gpart, gpart_elems);
+      r = gemm_big<double>(s, true, wd, c, m - c, 1.0, vc, ldv, vall + c, ldv, 0.0, gmat, wd,
+                           gpart, gpart_elems);
       if (r) return r;
       r = gemm_big<double>(s, false, wd, nc, c, -1.0, gmat, wd, wpall + (long long)cb * ldwa,
-                           ldwa, 0.0, (double*)wpart + (long long)got * nc * wd, wd, gpart,
-                           gpart_elems);
+                           ldwa, 0.0, part + (long long)got * nc * wd, wd, gpart, gpart_elems);
       if (r) return r;
       ++got;
     }
@@ -495,9 +541,10 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
                               (double*)A + i + (long long)c0 * lda, lda, gpart, gpart_elems);
         if (rc) return rc;
       }
-      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, wpart, nsp,
+      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, ll ? (const T*)wpw : wpart, nsp,
                              ll ? wpall + (long long)c0 * ldwa + i : wp, ll ? ldwa : ldw,
-                             frozen ? nullptr : B, ldb, c0, ncols, info, ll ? A : (T*)nullptr);
+                             frozen ? nullptr : B, ldb, c0, ncols, info, ll ? A : (T*)nullptr,
+                             ll ? pstr : 0);
       if (rc) return rc;
     }
     bool stop = false;

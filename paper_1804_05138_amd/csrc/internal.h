@@ -126,12 +126,13 @@ int launch_trail(hipStream_t s, int m, T* a, long long lda, int i, int bbu, int 
 // then R12 = A(i:i+bb, c) - V11 W'(:, c), X = R11^-1 R12 and
 // B(0:bb, c) -= Rhat11 X for the columns c = c0 .. c0 + ncols - 1 (skipped when
 // *info != 0).  Rhat11 = triu(B(0:bb, i:i+bb)).  With r12out (the matrix A
-// itself), R12 is also stored to rows i..i+bb of the columns.
+// itself), R12 is also stored to rows i..i+bb of the columns.  Partial z of W
+// starts at wpart + z pstride bb (pstride = 0: ncols).
 template <typename T>
 int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int bb,
                    const double* t, const T* wpart, int nsplit, double* wp, long long ldw,
                    double* bsk, long long ldb, int c0, int ncols, const int* info,
-                   T* r12out = nullptr);
+                   T* r12out = nullptr, long long pstride = 0);
 
 // Batched RQRCP (k_batched.hip): variant v of the persistent kernel.
 int batched_variants();

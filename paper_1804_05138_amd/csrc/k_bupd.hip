@@ -36,7 +36,7 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
                                                   double* __restrict__ wp, long long ldw,
                                                   double* __restrict__ bsk, long long ldb,
                                                   int c0, int ncols, const int* __restrict__ info,
-                                                  T* r12out) {
+                                                  T* r12out, long long pstride) {
   extern __shared__ double smem[];
   double* sT = smem;                 // T(q, r) at sT[r * AP + q]; later Rhat11(q, r)
   double* sA = sT + SB * AP;         // A(i + r, i + c) at sA[c * AP + r]
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
     for (int u = 0; u < NC; ++u) {
       const int e = tid + u * BT, c = e / SB, q = e % SB;
       const bool ok = c < nc && q < bb;
-      pv[u] = (double)wpart[((long long)sp * ncols + cb + (ok ? c : 0)) * bb + (ok ? q : 0)];
+      pv[u] = (double)wpart[((long long)sp * pstride + cb + (ok ? c : 0)) * bb + (ok ? q : 0)];
     }
 #pragma unroll
     for (int u = 0; u < NC; ++u) ws[u] += pv[u];
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* a, long long l
                                                   double* __restrict__ wp, long long ldw,
                                                   double* __restrict__ bsk, long long ldb,
                                                   int c0, int ncols, const int* __restrict__ info,
-                                                  T* r12out) {
+                                                  T* r12out, long long pstride) {
   extern __shared__ double smem[];
   double* sQ = smem;                 // quadrant: element (row r, column k) at sQ[k * QAP + r]
   double* sQ2 = sQ + QB * QAP;       // second quadrant, same layout
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* a, long long l
       for (int u = 0; u < NCQ; ++u) {
         const int e = tid + u * BT, c = e / (2 * QB), q = e % (2 * QB);
         const bool ok = c < nc && q < bb;
-        pv[u] = (double)wpart[((long long)sp * ncols + cb + (ok ? c : 0)) * bb + (ok ? q : 0)];
+        pv[u] = (double)wpart[((long long)sp * pstride + cb + (ok ? c : 0)) * bb + (ok ? q : 0)];
       }
 #pragma unroll
       for (int u = 0; u < NCQ; ++u) ws[u] += pv[u];
@@ -457,15 +457,17 @@ __global__ __launch_bounds__(BT) void k_bupdate_q(int m, const T* a, long long l
 template <typename T>
 int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int bb,
                    const double* t, const T* wpart, int nsplit, double* wp, long long ldw,
-                   double* bsk, long long ldb, int c0, int ncols, const int* info, T* r12out) {
+                   double* bsk, long long ldb, int c0, int ncols, const int* info, T* r12out,
+                   long long pstride) {
   if (ncols <= 0) return RQ_OK;
+  if (pstride <= 0) pstride = ncols;
   if (bb > MAX_B) return RQ_ERR_LIMIT;
   if (bb <= SB) {
     const size_t shmem = (2 * (size_t)SB * AP + 2 * (size_t)SB * SP + SB) * sizeof(double);
     RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bupdate_s<T>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
     hipLaunchKernelGGL(k_bupdate_s<T>, dim3((ncols + CW - 1) / CW), dim3(BT), shmem, s, m, a, lda,
-                       i, bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info, r12out);
+                       i, bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info, r12out, pstride);
     RQ_HIP_CHECK(hipGetLastError());
     return RQ_OK;
   }
@@ -474,15 +476,15 @@ int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int b
   RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bupdate_q<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   hipLaunchKernelGGL(k_bupdate_q<T>, dim3((ncols + QW - 1) / QW), dim3(BT), shmem, s, m, a, lda, i,
-                     bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info, r12out);
+                     bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info, r12out, pstride);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
 template int launch_bupdate<double>(hipStream_t, int, const double*, long long, int, int,
                                     const double*, const double*, int, double*, long long,
-                                    double*, long long, int, int, const int*, double*);
+                                    double*, long long, int, int, const int*, double*, long long);
 template int launch_bupdate<float>(hipStream_t, int, const float*, long long, int, int,
                                    const double*, const float*, int, double*, long long, double*,
-                                   long long, int, int, const int*, float*);
+                                   long long, int, int, const int*, float*, long long);
 
 }  // namespace rq

@@ -43,7 +43,7 @@ struct BigMfma<float> {
 
 constexpr int kPad = 1;  // LDS row padding (elements)
 
-template <typename T, bool TA, int WM, int WN, int BK, int OCC, bool VEC>
+template <typename T, bool TA, int WM, int WN, int BK, int OCC, int PF, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
     int M, int N, int K, T alpha, const T* __restrict__ A, long long lda, const T* __restrict__ B,
     long long ldb, T beta, T* __restrict__ C, long long ldc, int kchunk, T* __restrict__ part) {
@@ -74,7 +74,8 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
 
-  T ra[NLA * VW], rb[NLB * VW];
+  typedef T RegA[NLA * VW];
+  typedef T RegB[NLB * VW];
   // element (ci, oi) of a load: ci along the contiguous index (VW at a time)
   auto ld2 = [&](const T* p, bool ok0, bool ok1, T* dst) {
     if constexpr (VEC) {
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
       dst[0] = ok0 ? v : T(0);
     }
   };
-  auto load = [&](int k0) {
+  auto load = [&](int k0, RegA& ra, RegB& rb) {
 #pragma unroll
     for (int j = 0; j < NLA; ++j) {
       const int u = tid + NT * j;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
       ld2(B + (long long)gnc * ldb + gkc, gn < N && gk < ke, gn < N && gk + 1 < ke, rb + VW * j);
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int buf, const RegA& ra, const RegB& rb) {
 #pragma unroll
     for (int j = 0; j < NLA; ++j) {
       const int u = tid + NT * j;
@@ -134,15 +135,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
     }
   };
 
-  if (kb < ke) {
-    load(kb);
-    stash(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += BK) {
-    const bool more = k0 + BK < ke;
-    if (more) load(k0 + BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       T av[4], bv[4];
@@ -155,9 +148,51 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = BigMfma<T>::run(av[x], bv[y], acc[x][y]);
     }
-    if (more) stash(buf ^ 1);
+  };
+
+  if constexpr (PF == 1) {
+    RegA ra;
+    RegB rb;
+    if (kb < ke) {
+      load(kb, ra, rb);
+      stash(0, ra, rb);
+    }
     __syncthreads();
-    buf ^= 1;
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+      const bool more = k0 + BK < ke;
+      if (more) load(k0 + BK, ra, rb);
+      compute(buf);
+      if (more) stash(buf ^ 1, ra, rb);
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    // two steps of loads in flight while one runs: step t+1 and t+2 sit in the
+    // register sets of their parity.  Loads past the range read clamped
+    // addresses and go unused; they are issued unconditionally so that the
+    // wait for one set never covers the other.
+    const int nst = ke > kb ? (ke - kb + BK - 1) / BK : 0;  // uniform
+    if (nst > 0) {
+      RegA ra0, ra1;
+      RegB rb0, rb1;
+      load(kb, ra0, rb0);
+      load(kb + BK, ra1, rb1);
+      stash(0, ra0, rb0);
+      load(kb + 2 * BK, ra0, rb0);
+      __syncthreads();
+      for (int t = 0; t < nst; t += 2) {
+        compute(0);
+        if (t + 1 < nst) stash(1, ra1, rb1);
+        load(kb + (t + 3) * BK, ra1, rb1);
+        __syncthreads();
+        if (t + 1 >= nst) break;
+        compute(1);
+        if (t + 2 < nst) stash(0, ra0, rb0);
+        load(kb + (t + 4) * BK, ra0, rb0);
+        __syncthreads();
+      }
+    }
   }
 
 #pragma unroll
@@ -180,18 +215,145 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
       }
 }
 
-template <typename T, bool TA, int WM, int WN, int BK, int OCC>
+template <typename T, bool TA, int WM, int WN, int BK, int OCC, int PF = 1>
 void launch_big(hipStream_t s, bool vec, int M, int N, int K, T alpha, const T* A, long long lda,
                 const T* B, long long ldb, T beta, T* C, long long ldc, int kchunk, int nsplit,
                 T* part) {
   const int tiles = ((M + 64 * WM - 1) / (64 * WM)) * ((N + 64 * WN - 1) / (64 * WN));
   const dim3 grid(tiles, nsplit), block(64 * WM * WN);
   if (vec)
-    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, BK, OCC, true>), grid, block, 0, s, M, N, K,
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, BK, OCC, PF, true>), grid, block, 0, s, M, N, K,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
   else
-    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, BK, OCC, false>), grid, block, 0, s, M, N, K,
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, BK, OCC, PF, false>), grid, block, 0, s, M, N, K,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+}
+
+// W pass of the left-looking schedule: for K rows in split z,
+//     part[z][n][q] = sum_k V(k, q) B(k, n),   q < nq <= 64,
+// where the columns of B come from two segments (n < n1 from B1, the rest
+// from B2), so the V^T V_prev Gram block can ride along with V^T A2.
+// A wave owns 16 YN columns and all 64 rows q (4 YN MFMA tiles of 16 x 16);
+// each lane streams its B fragments straight from memory into registers: in a
+// chunk of KC rows, lane (g, c) loads the KC/4 consecutive rows g KC/4 ..
+// of its columns, and MFMA step j takes row g KC/4 + j from every lane group,
+// so no B data passes through LDS.  V (64 x KC per chunk, shared by the NW
+// waves) goes through LDS.  Two chunks of B are in flight
+// while one runs; loads past the range read clamped addresses and are never
+// used (issued unconditionally so that waiting for one chunk never waits for
+// the next).  Requires even leading dimensions, K and split ranges, and
+// 16-byte aligned bases (two-element loads).
+template <int KC, int YN, int NW, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, int n1,
+                                                   const double* __restrict__ V, long long ldv,
+                                                   const double* __restrict__ B1, long long ld1,
+                                                   const double* __restrict__ B2, long long ld2,
+                                                   int kchunk, double* __restrict__ part) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ double sV[2][KC][64 + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr16 = lane & 15, lg = lane >> 4;
+  constexpr int NT = 64 * NW;
+  const int n0 = (blockIdx.x * NW + wave) * 16 * YN;
+  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  const int nch = ke > kb ? (ke - kb + KC - 1) / KC : 0;  // uniform
+  if (nch == 0) return;
+
+  // this lane's YN columns
+  const double* bcol[YN];
+#pragma unroll
+  for (int y = 0; y < YN; ++y) {
+    int n = n0 + 16 * y + lr16;
+    n = n < N ? n : N - 1;
+    bcol[y] = n < n1 ? B1 + (long long)n * ld1 : B2 + (long long)(n - n1) * ld2;
+  }
+  constexpr int RL = KC / 4;  // rows per lane and chunk
+  typedef double RegB[YN][RL];
+  auto load_b = [&](int k0, RegB& r) {
+#pragma unroll
+    for (int y = 0; y < YN; ++y)
+#pragma unroll
+      for (int p = 0; p < RL / 2; ++p) {
+        const int k = k0 + RL * lg + 2 * p;
+        const d2 v = *reinterpret_cast<const d2*>(bcol[y] + (k < ke ? k : ke - 2));
+        r[y][2 * p] = k < ke ? v.x : 0.0;
+        r[y][2 * p + 1] = k + 1 < ke ? v.y : 0.0;
+      }
+  };
+  // V chunk: KC rows x 64 columns, pairs along the rows
+  constexpr int NV = KC * 32 / NT;  // pairs per thread
+  static_assert(NV * NT == KC * 32, "V chunk splits evenly");
+  double rv[2 * NV];
+  auto load_v = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int u = tid + NT * j;
+      const int ki = (u % (KC / 2)) * 2, q = u / (KC / 2);
+      const int k = k0 + ki;
+      const d2 v = *reinterpret_cast<const d2*>(V + (long long)(q < nq ? q : nq - 1) * ldv +
+                                                (k < ke ? k : ke - 2));
+      rv[2 * j] = (q < nq && k < ke) ? v.x : 0.0;
+      rv[2 * j + 1] = (q < nq && k + 1 < ke) ? v.y : 0.0;
+    }
+  };
+  auto stash_v = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int u = tid + NT * j;
+      const int ki = (u % (KC / 2)) * 2, q = u / (KC / 2);
+      sV[buf][ki][q] = rv[2 * j];
+      sV[buf][ki + 1][q] = rv[2 * j + 1];
+    }
+  };
+  v4d acc[4][YN];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < YN; ++y) acc[x][y] = v4d{0, 0, 0, 0};
+  auto compute = [&](int buf, const RegB& r) {
+#pragma unroll
+    for (int j = 0; j < RL; ++j) {
+      double av[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) av[x] = sV[buf][RL * lg + j][16 * x + lr16];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < YN; ++y) acc[x][y] = mfma_f64(av[x], r[y][j], acc[x][y]);
+    }
+  };
+
+  RegB r0, r1;
+  load_b(kb, r0);
+  load_v(kb);
+  load_b(kb + KC, r1);
+  stash_v(0);
+  load_v(kb + KC);
+  __syncthreads();
+  for (int t = 0; t < nch; t += 2) {
+    compute(0, r0);
+    stash_v(1);
+    load_v(kb + (t + 2) * KC);
+    load_b(kb + (t + 2) * KC, r0);
+    __syncthreads();
+    if (t + 1 >= nch) break;
+    compute(1, r1);
+    stash_v(0);
+    load_v(kb + (t + 3) * KC);
+    load_b(kb + (t + 3) * KC, r1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < YN; ++y) {
+      const int n = n0 + 16 * y + lr16;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int q = 16 * x + lg + 4 * e;
+        if (n < N && q < nq) part[((size_t)blockIdx.y * N + n) * nq + q] = acc[x][y][e];
+      }
+    }
 }
 
 // C = alpha sum_z part[z] + beta C (partials in split order)
@@ -303,6 +465,30 @@ int gemm_big_partials(hipStream_t s, bool ta, int M, int N, int K, const T* A, l
   int kchunk = 1, nsplit = 1;
   big_split(K, max_split, &kchunk, &nsplit);
   big_launch<T>(s, ta, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, 0, kchunk, nsplit, part);
+  RQ_HIP_CHECK(hipGetLastError());
+  *nsplit_out = nsplit;
+  return RQ_OK;
+}
+
+int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const double* V, long long ldv,
+                   const double* B1, long long ld1, const double* B2, long long ld2,
+                   double* part, int max_split, int* nsplit_out) {
+  *nsplit_out = 0;
+  if (N <= 0 || nq <= 0) return RQ_OK;
+  if (nq > 64) return RQ_ERR_LIMIT;
+  const uintptr_t al = 16;
+  const bool fits = K >= 2 && K % 2 == 0 && ldv % 2 == 0 && ld1 % 2 == 0 && ld2 % 2 == 0 &&
+                    reinterpret_cast<uintptr_t>(V) % al == 0 &&
+                    reinterpret_cast<uintptr_t>(B1) % al == 0 &&
+                    (n1 >= N || reinterpret_cast<uintptr_t>(B2) % al == 0);
+  if (!fits) return RQ_ERR_LIMIT;
+  constexpr int KC = 32, YN = 2, NW = 8;
+  int want = std::max(1, max_split);
+  int kchunk = ((K + want - 1) / want + KC - 1) / KC * KC;
+  const int nsplit = (K + kchunk - 1) / kchunk;
+  constexpr int cols = 16 * YN * NW;
+  hipLaunchKernelGGL((k_wpass<KC, YN, NW, 1>), dim3((N + cols - 1) / cols, nsplit), dim3(64 * NW),
+                     0, s, K, nq, N, n1, V, ldv, B1, ld1, B2, ld2, kchunk, part);
   RQ_HIP_CHECK(hipGetLastError());
   *nsplit_out = nsplit;
   return RQ_OK;

@@ -171,7 +171,7 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   L.wp = take((size_t)b * n * sizeof(double));
   L.vall = take(L.ll ? (size_t)L.ldv * k * sizeof(double) : 0);
   L.wpall = take(L.ll ? (size_t)L.ldwa * n * sizeof(double) : 0);
-  L.gmat = take(L.ll ? (size_t)b * k * sizeof(double) : 0);
+  L.gmat = take(L.ll ? (size_t)2 * b * k * sizeof(double) : 0);
   L.gpart = take(L.ll ? ll_split_elems(m, n, k, b) * sizeof(double) : 0);
   L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * es : 0);
   L.mark = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)n * sizeof(int) : 0);
@@ -250,14 +250,43 @@ __global__ void k_perm_check(int n, const int* __restrict__ perm, int* __restric
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
-// out[e] = sum_z p[z stride + e], e < count (partials added in order)
-__global__ void k_sum_parts(long long count, int nparts, long long stride,
-                            const double* __restrict__ p, double* __restrict__ out) {
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+// L (2w x c, leading dimension 2w) of the stacked correction product: rows
+// 0..w-1 are V(c0 + r, 0:c) (the block's own rows of the earlier reflectors),
+// rows w..2w-1 the Gram block G = sum of the nparts partials of G (each at
+// stride gstride), or left as they are when nparts = 0.
+__global__ void k_build_l(int w, int c, int c0, const double* __restrict__ v, long long ldv,
+                          int nparts, long long gstride, const double* __restrict__ gp,
+                          double* __restrict__ l) {
+  const long long total = 2LL * w * c;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % (2 * w)), col = (int)(e / (2 * w));
+    if (r < w) {
+      l[e] = v[(long long)col * ldv + c0 + r];
+    } else if (nparts > 0) {
+      const long long g = (long long)col * w + (r - w);
+      double acc = gp[g];
+      for (int z = 1; z < nparts; ++z) acc += gp[(long long)z * gstride + g];
+      l[e] = acc;
+    }
+  }
+}
+
+// The stacked correction P = L W' (partials, 2w x nc each): rows 0..w-1 are
+// subtracted from A(c0 .. c0+w-1, cols), rows w..2w-1 negated into the W
+// correction partial (leading dimension w).
+__global__ void k_apply_corr(int w, int nc, int nparts, const double* __restrict__ p,
+                             double* __restrict__ a, long long lda, double* __restrict__ wslot) {
+  const long long total = 2LL * w * nc;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     double acc = p[e];
-    for (int z = 1; z < nparts; ++z) acc += p[(long long)z * stride + e];
-    out[e] = acc;
+    for (int z = 1; z < nparts; ++z) acc += p[(long long)z * total + e];
+    const int r = (int)(e % (2 * w)), col = (int)(e / (2 * w));
+    if (r < w)
+      a[(long long)col * lda + r] -= acc;
+    else
+      wslot[(long long)col * w + (r - w)] = -acc;
   }
 }
 
@@ -372,6 +401,28 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     RQ_HIP_CHECK(hipGetLastError());
     return 0;
   };
+  // Corrections of block (c, wd) from all earlier blocks, one product with
+  // L = [V(c:c+wd, 0:c); G] (in gmat, 2 wd x c): the block's rows of the
+  // trailing columns, A(c:c+wd, c+wd:n) -= V(c:c+wd, 0:c) W'(0:c, .), and the
+  // W partial -G W'(0:c, .) at wslot.
+  auto stacked_corr = [&](int c, int wd, double* wslot) -> int {
+    const int cb = c + wd, nc = n - cb;
+    PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * wd * (double)c * nc, 8.0 * (double)c * nc);
+    const int tiles = ((2 * wd + 127) / 128) * ((nc + 127) / 128);
+    int sp = (1024 + tiles - 1) / tiles;
+    sp = std::min(sp, std::max(1, c / 32));
+    sp = (int)std::min<long long>(sp, (long long)(gpart_elems / ((size_t)2 * wd * nc)));
+    sp = std::max(sp, 1);
+    int got = 0;
+    int r = gemm_big_partials<double>(s, false, 2 * wd, nc, c, gmat, 2 * wd,
+                                      wpall + (long long)cb * ldwa, ldwa, gpart, sp, &got);
+    if (r) return r;
+    hipLaunchKernelGGL(k_apply_corr, dim3(grid_for(2LL * wd * nc)), dim3(256), 0, s, wd, nc, got,
+                       (const double*)gpart, (double*)A + c + (long long)cb * lda, (long long)lda,
+                       wslot);
+    RQ_HIP_CHECK(hipGetLastError());
+    return 0;
+  };
   // W partials of block (c, wd) over the trailing columns c+wd .. n: the read
   // pass V^T A2 (split over rows) and, after the first block, the correction
   // -(V^T V_<c) W'(0:c, .) as one more partial.  *nsp_out = partials written;
@@ -404,14 +455,10 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       wpw = part + (long long)c * wd;
       pstr = nt;
       if (c > 0) {
-        PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)c * nc, 8.0 * (double)c * nc);
-        hipLaunchKernelGGL(k_sum_parts, dim3(grid_for((long long)c * wd)), dim3(256), 0, s,
-                           (long long)c * wd, got, (long long)nt * wd, (const double*)part, gmat);
+        hipLaunchKernelGGL(k_build_l, dim3(grid_for(2LL * wd * c)), dim3(256), 0, s, wd, c, c, vall,
+                           ldv, got, (long long)nt * wd, (const double*)part, gmat);
         RQ_HIP_CHECK(hipGetLastError());
-        r = gemm_big<double>(s, false, wd, nc, c, -1.0, gmat, wd, wpall + (long long)cb * ldwa,
-                             ldwa, 0.0, part + ((long long)got * nt + c) * wd, wd, gpart,
-                             gpart_elems);
-        if (r) return r;
+        if ((r = stacked_corr(c, wd, part + ((long long)got * nt + c) * wd))) return r;
         ++got;
       }
       *nsp_out = got;
@@ -430,14 +477,17 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       if (r) return r;
     }
     if (c > 0) {
-      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)c * ((m - c) + nc),
-                    8.0 * (double)c * ((m - c) + nc));
-      r = gemm_big<double>(s, true, wd, c, m - c, 1.0, vc, ldv, vall + c, ldv, 0.0, gmat, wd,
-                           gpart, gpart_elems);
-      if (r) return r;
-      r = gemm_big<double>(s, false, wd, nc, c, -1.0, gmat, wd, wpall + (long long)cb * ldwa,
-                           ldwa, 0.0, part + (long long)got * nc * wd, wd, gpart, gpart_elems);
-      if (r) return r;
+      {
+        PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)c * (m - c),
+                      8.0 * (double)c * (m - c));
+        r = gemm_big<double>(s, true, wd, c, m - c, 1.0, vc, ldv, vall + c, ldv, 0.0, gmat + wd,
+                             2 * wd, gpart, gpart_elems);
+        if (r) return r;
+      }
+      hipLaunchKernelGGL(k_build_l, dim3(grid_for(2LL * wd * c)), dim3(256), 0, s, wd, c, c, vall,
+                         ldv, 0, 0LL, (const double*)nullptr, gmat);
+      RQ_HIP_CHECK(hipGetLastError());
+      if ((r = stacked_corr(c, wd, part + (long long)got * nc * wd))) return r;
       ++got;
     }
     *nsp_out = got;
@@ -532,15 +582,8 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     const int c0 = i + bb;
     const int ncols = n - c0;
     if (ncols > 0) {
-      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * bb * (double)bb * ncols + 2.0 * bb * (double)i * ncols,
+      PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * bb * (double)bb * ncols,
                     8.0 * ncols * (double)bb * (nsp + 4));
-      if (ll && i > 0) {
-        // rows i..i+bb of the trailing columns take the updates of the earlier blocks
-        rc = gemm_big<double>(s, false, bb, ncols, i, -1.0, vall + i, ldv,
-                              wpall + (long long)c0 * ldwa, ldwa, 1.0,
-                              (double*)A + i + (long long)c0 * lda, lda, gpart, gpart_elems);
-        if (rc) return rc;
-      }
       rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, ll ? (const T*)wpw : wpart, nsp,
                              ll ? wpall + (long long)c0 * ldwa + i : wp, ll ? ldwa : ldw,
                              frozen ? nullptr : B, ldb, c0, ncols, info, ll ? A : (T*)nullptr,

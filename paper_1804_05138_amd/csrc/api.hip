@@ -163,7 +163,9 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   L.pscr = PSCR_OFF;
   L.ppart = take(panel_partial_doubles(m, std::min(b, k)) * sizeof(double));
   L.tmat = take((size_t)MAX_B * MAX_B * sizeof(double));
-  L.ll = prm.a_type == RQRCP_F64;
+  // left-looking for FP64 when the rank is at most half the width: its Gram
+  // blocks V_j^T V_<j add about m k^2 flops to the 4 m n k of the updates
+  L.ll = prm.a_type == RQRCP_F64 && 2LL * k <= n;
   L.ldv = m + (m & 1);
   L.ldwa = k + (k & 1);
   L.wpart = take(std::max(wpart_doubles(m, n, k, b),

@@ -2,13 +2,13 @@
 //     C = alpha op(A) B + beta C     (column-major, op(A) = A or A^T),
 // or, for a split reduction, the raw partial sums of K ranges.
 //
-// Each wave owns a 64 x 64 block of C (4 x 4 MFMA tiles of 16 x 16, FP64
-// v_mfma_f64_16x16x4f64 or FP32 v_mfma_f32_16x16x4f32); a workgroup of WM x WN
-// waves covers a (64 WM) x (64 WN) tile.  K advances in steps of BK through two
-// LDS buffers: the global loads of step t+1 are in registers while step t runs
-// on the matrix cores, one barrier per step.  With 64 x 64 per wave every LDS
-// operand read feeds four MFMAs, twice the reuse of the 32 x 32 wave blocks of
-// the generic GEMM (k_gemm.hip).
+// Each wave owns a (16 XT) x (16 YT) block of C (XT x YT MFMA tiles of 16 x 16,
+// FP64 v_mfma_f64_16x16x4f64 or FP32 v_mfma_f32_16x16x4f32); a workgroup of
+// WM x WN waves covers a (16 XT WM) x (16 YT WN) tile.  K advances in steps of
+// BK through two LDS buffers: the global loads of step t+1 are in registers
+// while step t runs on the matrix cores, one barrier per step.  The large
+// products use 128 x 128 tiles (twice the side of the generic GEMM's,
+// k_gemm.hip), so each operand byte staged feeds twice the MFMA work.
 //
 // Loads move two consecutive elements of the contiguous index per lane
 // (8- or 16-byte vector loads) when leading dimensions, bases and the
@@ -43,13 +43,13 @@ struct BigMfma<float> {
 
 constexpr int kPad = 1;  // LDS row padding (elements)
 
-template <typename T, bool TA, int WM, int WN, int BK, int OCC, int PF, bool VEC>
+template <typename T, bool TA, int WM, int WN, int XT, int YT, int BK, int OCC, int PF, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
     int M, int N, int K, T alpha, const T* __restrict__ A, long long lda, const T* __restrict__ B,
     long long ldb, T beta, T* __restrict__ C, long long ldc, int kchunk, T* __restrict__ part) {
   typedef typename BigMfma<T>::acc_t acc_t;
   typedef T T2 __attribute__((ext_vector_type(2)));
-  constexpr int NT = 64 * WM * WN, BM = 64 * WM, BN = 64 * WN;
+  constexpr int NT = 64 * WM * WN, BM = 16 * XT * WM, BN = 16 * YT * WN;
   constexpr int VW = VEC ? 2 : 1;
   constexpr int NLA = BM * BK / NT / VW, NLB = BN * BK / NT / VW;
   static_assert(NLA * NT * VW == BM * BK && NLB * NT * VW == BN * BK, "tiles split evenly");
@@ -65,14 +65,14 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
   const int first = tile / (GM * nbn) * GM, gsz = min(nbm - first, GM);
   const int tm = first + (tile % (GM * nbn)) % gsz, tn = (tile % (GM * nbn)) / gsz;
   const int m0 = tm * BM, n0 = tn * BN;
-  const int wm = (wave % WM) * 64, wn = (wave / WM) * 64;
+  const int wm = (wave % WM) * 16 * XT, wn = (wave / WM) * 16 * YT;
   const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
 
-  acc_t acc[4][4];
+  acc_t acc[XT][YT];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < XT; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
+    for (int y = 0; y < YT; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
 
   typedef T RegA[NLA * VW];
   typedef T RegB[NLB * VW];
@@ -138,15 +138,15 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
   auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
-      T av[4], bv[4];
+      T av[XT], bv[YT];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) av[x] = sA[buf][4 * ks + lg][wm + 16 * x + lr16];
+      for (int x = 0; x < XT; ++x) av[x] = sA[buf][4 * ks + lg][wm + 16 * x + lr16];
 #pragma unroll
-      for (int y = 0; y < 4; ++y) bv[y] = sB[buf][4 * ks + lg][wn + 16 * y + lr16];
+      for (int y = 0; y < YT; ++y) bv[y] = sB[buf][4 * ks + lg][wn + 16 * y + lr16];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < XT; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = BigMfma<T>::run(av[x], bv[y], acc[x][y]);
+        for (int y = 0; y < YT; ++y) acc[x][y] = BigMfma<T>::run(av[x], bv[y], acc[x][y]);
     }
   };
 
@@ -196,9 +196,9 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
   }
 
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < XT; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < YT; ++y)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gm = m0 + wm + 16 * x + acc_row<T>(lg, e);
@@ -215,17 +215,18 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
       }
 }
 
-template <typename T, bool TA, int WM, int WN, int BK, int OCC, int PF = 1>
+template <typename T, bool TA, int WM, int WN, int BK, int OCC, int PF = 1, int XT = 4, int YT = 4>
 void launch_big(hipStream_t s, bool vec, int M, int N, int K, T alpha, const T* A, long long lda,
                 const T* B, long long ldb, T beta, T* C, long long ldc, int kchunk, int nsplit,
                 T* part) {
-  const int tiles = ((M + 64 * WM - 1) / (64 * WM)) * ((N + 64 * WN - 1) / (64 * WN));
+  constexpr int BM = 16 * XT * WM, BN = 16 * YT * WN;
+  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   const dim3 grid(tiles, nsplit), block(64 * WM * WN);
   if (vec)
-    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, BK, OCC, PF, true>), grid, block, 0, s, M, N, K,
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, PF, true>), grid, block, 0, s, M, N, K,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
   else
-    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, BK, OCC, PF, false>), grid, block, 0, s, M, N, K,
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, PF, false>), grid, block, 0, s, M, N, K,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
 }
 
@@ -411,9 +412,9 @@ void big_launch(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A
     else if (N <= 64)
       launch_big<T, false, 2, 1, kBK, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
                                          kchunk, nsplit, part);
-    else
-      launch_big<T, false, 2, 2, kBK, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                         kchunk, nsplit, part);
+    else  // 128 x 128 tiles as eight waves of 32 x 64 (two workgroups per CU)
+      launch_big<T, false, 4, 2, kBK, 2, 1, 2, 4>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                  ldc, kchunk, nsplit, part);
   }
 }
 

@@ -561,7 +561,7 @@ def main():
         "pct_fp64_mfma_peak": round(100.0 * tflops / PEAK_FP64_MFMA, 2),
         "phases_ms_per_step": {ph: round(v[0] / args.steps, 3) for ph, v in phases.items() if v[1]},
         "roofline": {
-            "kernel": "k_gemm_big<double, TA> (per-block W = V^T A2 pass, left-looking)",
+            "kernel": "k_wpass (per-block W = V^T [V_prev | A2] pass of the left-looking update)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
             "peak": PEAK_FP64_MFMA,

@@ -483,12 +483,12 @@ int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const double* V,
                     reinterpret_cast<uintptr_t>(B1) % al == 0 &&
                     (n1 >= N || reinterpret_cast<uintptr_t>(B2) % al == 0);
   if (!fits) return RQ_ERR_LIMIT;
-  constexpr int KC = 32, YN = 2, NW = 8;
+  constexpr int KC = 16, YN = 2, NW = 8;   // two workgroups of eight waves per CU
   int want = std::max(1, max_split);
   int kchunk = ((K + want - 1) / want + KC - 1) / KC * KC;
   const int nsplit = (K + kchunk - 1) / kchunk;
   constexpr int cols = 16 * YN * NW;
-  hipLaunchKernelGGL((k_wpass<KC, YN, NW, 1>), dim3((N + cols - 1) / cols, nsplit), dim3(64 * NW),
+  hipLaunchKernelGGL((k_wpass<KC, YN, NW, 2>), dim3((N + cols - 1) / cols, nsplit), dim3(64 * NW),
                      0, s, K, nq, N, n1, V, ldv, B1, ld1, B2, ld2, kchunk, part);
   RQ_HIP_CHECK(hipGetLastError());
   *nsplit_out = nsplit;

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rqrcp.h"
@@ -165,16 +166,16 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   L.tmat = take((size_t)MAX_B * MAX_B * sizeof(double));
   // left-looking for FP64 when the rank is at most half the width: its Gram
   // blocks V_j^T V_<j add about m k^2 flops to the 4 m n k of the updates
-  L.ll = prm.a_type == RQRCP_F64 && 2LL * k <= n;
+  L.ll = 2LL * k <= n;
   L.ldv = m + (m & 1);
   L.ldwa = k + (k & 1);
   L.wpart = take(std::max(wpart_doubles(m, n, k, b),
                           L.ll ? (size_t)(kLLSplit + 1) * n * b : (size_t)0) * es);
   L.wp = take((size_t)b * n * sizeof(double));
-  L.vall = take(L.ll ? (size_t)L.ldv * k * sizeof(double) : 0);
-  L.wpall = take(L.ll ? (size_t)L.ldwa * n * sizeof(double) : 0);
-  L.gmat = take(L.ll ? (size_t)2 * b * k * sizeof(double) : 0);
-  L.gpart = take(L.ll ? ll_split_elems(m, n, k, b) * sizeof(double) : 0);
+  L.vall = take(L.ll ? (size_t)L.ldv * k * es : 0);
+  L.wpall = take(L.ll ? (size_t)L.ldwa * n * es : 0);
+  L.gmat = take(L.ll ? (size_t)2 * b * k * es : 0);
+  L.gpart = take(L.ll ? ll_split_elems(m, n, k, b) * es : 0);
   L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * es : 0);
   L.mark = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)n * sizeof(int) : 0);
   L.formq = take(form_q_work_elems(m, k, b) * es);
@@ -256,9 +257,10 @@ __global__ void k_set_int(int* p, int v) { *p = v; }
 // 0..w-1 are V(c0 + r, 0:c) (the block's own rows of the earlier reflectors),
 // rows w..2w-1 the Gram block G = sum of the nparts partials of G (each at
 // stride gstride), or left as they are when nparts = 0.
-__global__ void k_build_l(int w, int c, int c0, const double* __restrict__ v, long long ldv,
-                          int nparts, long long gstride, const double* __restrict__ gp,
-                          double* __restrict__ l) {
+template <typename T>
+__global__ void k_build_l(int w, int c, int c0, const T* __restrict__ v, long long ldv,
+                          int nparts, long long gstride, const T* __restrict__ gp,
+                          T* __restrict__ l) {
   const long long total = 2LL * w * c;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
@@ -267,7 +269,7 @@ __global__ void k_build_l(int w, int c, int c0, const double* __restrict__ v, lo
       l[e] = v[(long long)col * ldv + c0 + r];
     } else if (nparts > 0) {
       const long long g = (long long)col * w + (r - w);
-      double acc = gp[g];
+      T acc = gp[g];
       for (int z = 1; z < nparts; ++z) acc += gp[(long long)z * gstride + g];
       l[e] = acc;
     }
@@ -277,12 +279,13 @@ __global__ void k_build_l(int w, int c, int c0, const double* __restrict__ v, lo
 // The stacked correction P = L W' (partials, 2w x nc each): rows 0..w-1 are
 // subtracted from A(c0 .. c0+w-1, cols), rows w..2w-1 negated into the W
 // correction partial (leading dimension w).
-__global__ void k_apply_corr(int w, int nc, int nparts, const double* __restrict__ p,
-                             double* __restrict__ a, long long lda, double* __restrict__ wslot) {
+template <typename T>
+__global__ void k_apply_corr(int w, int nc, int nparts, const T* __restrict__ p,
+                             T* __restrict__ a, long long lda, T* __restrict__ wslot) {
   const long long total = 2LL * w * nc;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    double acc = p[e];
+    T acc = p[e];
     for (int z = 1; z < nparts; ++z) acc += p[(long long)z * total + e];
     const int r = (int)(e % (2 * w)), col = (int)(e / (2 * w));
     if (r < w)
@@ -297,13 +300,27 @@ __global__ void k_apply_corr(int w, int nc, int nparts, const double* __restrict
 // trapezoidal V of Alg. 2's block, kept for the left-looking products).
 template <typename T>
 __global__ void k_copy_v(int m, int c, int w, const T* __restrict__ a, long long lda,
-                         double* __restrict__ v, long long ldv) {
+                         T* __restrict__ v, long long ldv) {
   const long long total = (long long)m * w;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const int q = (int)(e / m), r = (int)(e % m);
     const int d = r - (c + q);
-    v[(long long)(c + q) * ldv + r] = d > 0 ? (double)a[(long long)(c + q) * lda + r] : (d == 0 ? 1.0 : 0.0);
+    v[(long long)(c + q) * ldv + r] = d > 0 ? a[(long long)(c + q) * lda + r] : T(d == 0 ? 1 : 0);
+  }
+}
+
+// W'(i:i+w, c0 + c) = wp(0:w, c) in the storage type, c < nc (FP32 storage:
+// the sample-update kernel forms W' in FP64; the left-looking products apply
+// it in FP32, as the fused pass does)
+template <typename T>
+__global__ void k_store_w(int w, int nc, const double* __restrict__ wp, long long ldw,
+                          T* __restrict__ dst, long long ldd) {
+  const long long total = (long long)w * nc;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(e / w), r = (int)(e % w);
+    dst[(long long)c * ldd + r] = (T)wp[(long long)c * ldw + r];
   }
 }
 
@@ -391,10 +408,10 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   // per-block product W_j = V_j^T A2 reads the original A2 and subtracts
   // (V_j^T V_<j) W'_<j, and A2 -= V W' runs once at the end.
   const bool ll = L.ll;
-  double* vall = (double*)(w + L.vall);
-  double* wpall = (double*)(w + L.wpall);
-  double* gmat = (double*)(w + L.gmat);
-  double* gpart = (double*)(w + L.gpart);
+  T* vall = (T*)(w + L.vall);
+  T* wpall = (T*)(w + L.wpall);
+  T* gmat = (T*)(w + L.gmat);
+  T* gpart = (T*)(w + L.gpart);
   const long long ldv = L.ldv, ldwa = L.ldwa;
   const size_t gpart_elems = ll ? ll_split_elems(m, n, k, b) : 0;
   auto copy_v = [&](int c, int wd) -> int {
@@ -407,7 +424,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   // L = [V(c:c+wd, 0:c); G] (in gmat, 2 wd x c): the block's rows of the
   // trailing columns, A(c:c+wd, c+wd:n) -= V(c:c+wd, 0:c) W'(0:c, .), and the
   // W partial -G W'(0:c, .) at wslot.
-  auto stacked_corr = [&](int c, int wd, double* wslot) -> int {
+  auto stacked_corr = [&](int c, int wd, T* wslot) -> int {
     const int cb = c + wd, nc = n - cb;
     PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * wd * (double)c * nc, 8.0 * (double)c * nc);
     const int tiles = ((2 * wd + 127) / 128) * ((nc + 127) / 128);
@@ -416,12 +433,11 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     sp = (int)std::min<long long>(sp, (long long)(gpart_elems / ((size_t)2 * wd * nc)));
     sp = std::max(sp, 1);
     int got = 0;
-    int r = gemm_big_partials<double>(s, false, 2 * wd, nc, c, gmat, 2 * wd,
-                                      wpall + (long long)cb * ldwa, ldwa, gpart, sp, &got);
+    int r = gemm_big_partials<T>(s, false, 2 * wd, nc, c, gmat, 2 * wd,
+                                 wpall + (long long)cb * ldwa, ldwa, gpart, sp, &got);
     if (r) return r;
-    hipLaunchKernelGGL(k_apply_corr, dim3(grid_for(2LL * wd * nc)), dim3(256), 0, s, wd, nc, got,
-                       (const double*)gpart, (double*)A + c + (long long)cb * lda, (long long)lda,
-                       wslot);
+    hipLaunchKernelGGL(k_apply_corr<T>, dim3(grid_for(2LL * wd * nc)), dim3(256), 0, s, wd, nc,
+                       got, (const T*)gpart, A + c + (long long)cb * lda, (long long)lda, wslot);
     RQ_HIP_CHECK(hipGetLastError());
     return 0;
   };
@@ -429,16 +445,16 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   // pass V^T A2 (split over rows) and, after the first block, the correction
   // -(V^T V_<c) W'(0:c, .) as one more partial.  *nsp_out = partials written;
   // partial z of W starts at wpw + z pstr wd (pstr = 0: n - c - wd columns).
-  double* wpw = (double*)wpart;
+  T* wpw = wpart;
   long long pstr = 0;
   auto w_pass = [&](int c, int wd, int* nsp_out) -> int {
     const int cb = c + wd, nc = n - cb;
     *nsp_out = 0;
-    wpw = (double*)wpart;
+    wpw = wpart;
     pstr = 0;
     if (nc <= 0) return 0;
-    double* part = (double*)wpart;
-    const double* vc = vall + c + (long long)c * ldv;  // V_c, rows c .. m
+    T* part = wpart;
+    const T* vc = vall + c + (long long)c * ldv;  // V_c, rows c .. m
     int got = 0, r = 0;
     // one pass over [V(c:m, 0:c) | A(c:m, cb:n)]: the Gram block G = V_c^T V_<c
     // rides along with W = V_c^T A2
@@ -449,16 +465,16 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       sp = std::max(1, std::min(sp, std::min(kLLSplit, (m - c) / 256)));
       PhaseTimer pt(h, RQRCP_PHASE_TRAIL, 2.0 * (m - c) * (double)wd * nt,
                     8.0 * (m - c) * (double)nt);
-      r = wpass_partials(s, m - c, wd, nt, c, vc, ldv, vall + c, ldv,
-                         (const double*)A + c + (long long)cb * lda, lda, part, sp, &got);
+      r = wpass_partials<T>(s, m - c, wd, nt, c, vc, ldv, vall + c, ldv,
+                            (const T*)A + c + (long long)cb * lda, lda, part, sp, &got);
       if (r && r != RQ_ERR_LIMIT) return r;
     }
     if (r == 0) {
       wpw = part + (long long)c * wd;
       pstr = nt;
       if (c > 0) {
-        hipLaunchKernelGGL(k_build_l, dim3(grid_for(2LL * wd * c)), dim3(256), 0, s, wd, c, c, vall,
-                           ldv, got, (long long)nt * wd, (const double*)part, gmat);
+        hipLaunchKernelGGL(k_build_l<T>, dim3(grid_for(2LL * wd * c)), dim3(256), 0, s, wd, c, c,
+                           (const T*)vall, ldv, got, (long long)nt * wd, (const T*)part, gmat);
         RQ_HIP_CHECK(hipGetLastError());
         if ((r = stacked_corr(c, wd, part + ((long long)got * nt + c) * wd))) return r;
         ++got;
@@ -473,21 +489,20 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       sp = std::max(1, std::min(sp, std::min(kLLSplit, (m - c) / 256)));
       PhaseTimer pt(h, RQRCP_PHASE_TRAIL, 2.0 * (m - c) * (double)wd * nc,
                     8.0 * (m - c) * (double)nc);
-      r = gemm_big_partials<double>(s, true, wd, nc, m - c, vc, ldv,
-                                    (const double*)A + c + (long long)cb * lda, lda, part, sp,
-                                    &got);
+      r = gemm_big_partials<T>(s, true, wd, nc, m - c, vc, ldv,
+                               (const T*)A + c + (long long)cb * lda, lda, part, sp, &got);
       if (r) return r;
     }
     if (c > 0) {
       {
         PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)c * (m - c),
                       8.0 * (double)c * (m - c));
-        r = gemm_big<double>(s, true, wd, c, m - c, 1.0, vc, ldv, vall + c, ldv, 0.0, gmat + wd,
-                             2 * wd, gpart, gpart_elems);
+        r = gemm_big<T>(s, true, wd, c, m - c, T(1), vc, ldv, vall + c, ldv, T(0), gmat + wd,
+                        2 * wd, gpart, gpart_elems);
         if (r) return r;
       }
-      hipLaunchKernelGGL(k_build_l, dim3(grid_for(2LL * wd * c)), dim3(256), 0, s, wd, c, c, vall,
-                         ldv, 0, 0LL, (const double*)nullptr, gmat);
+      hipLaunchKernelGGL(k_build_l<T>, dim3(grid_for(2LL * wd * c)), dim3(256), 0, s, wd, c, c,
+                         (const T*)vall, ldv, 0, 0LL, (const T*)nullptr, gmat);
       RQ_HIP_CHECK(hipGetLastError());
       if ((r = stacked_corr(c, wd, part + (long long)got * nc * wd))) return r;
       ++got;
@@ -558,7 +573,8 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       if (rc) return rc;
     }
     PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
-    rc = launch_apply_pairs<T>(s, m, A, lda, 0, jpvt, nullptr, 0, 0, 0, pairs, &qscr->npairs,
+    rc = launch_apply_pairs<T>(s, m, A, lda, 0, jpvt, (double*)nullptr, 0, 0, 0, pairs,
+                               &qscr->npairs,
                                2 * bb);
     if (rc) return rc;
   }
@@ -586,11 +602,25 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     if (ncols > 0) {
       PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * bb * (double)bb * ncols,
                     8.0 * ncols * (double)bb * (nsp + 4));
-      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, ll ? (const T*)wpw : wpart, nsp,
-                             ll ? wpall + (long long)c0 * ldwa + i : wp, ll ? ldwa : ldw,
-                             frozen ? nullptr : B, ldb, c0, ncols, info, ll ? A : (T*)nullptr,
-                             ll ? pstr : 0);
+      // W' in FP64 goes straight into the W' rows; in FP32 storage through wp
+      double* wout = wp;
+      long long ldwo = ldw;
+      if constexpr (std::is_same<T, double>::value) {
+        if (ll) {
+          wout = wpall + (long long)c0 * ldwa + i;
+          ldwo = ldwa;
+        }
+      }
+      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, ll ? (const T*)wpw : wpart, nsp, wout,
+                             ldwo, frozen ? nullptr : B, ldb, c0, ncols, info,
+                             ll ? A : (T*)nullptr, ll ? pstr : 0);
       if (rc) return rc;
+      if (ll && !std::is_same<T, double>::value) {
+        hipLaunchKernelGGL(k_store_w<T>, dim3(grid_for((long long)bb * ncols)), dim3(256), 0, s,
+                           bb, ncols, (const double*)wp, ldw, wpall + (long long)c0 * ldwa + i,
+                           ldwa);
+        RQ_HIP_CHECK(hipGetLastError());
+      }
     }
     bool stop = false;
     if (tol > 0.0 && ncols > 0) {
@@ -610,8 +640,8 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
         }
         PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
         if (ll)
-          rc = launch_apply_pairs<T>(s, m, A, lda, c0, jpvt, wpall + (long long)c0 * ldwa, c0,
-                                     ldwa, 0, pairs, &qscr->npairs, 2 * bbn);
+          rc = launch_apply_pairs<T, T>(s, m, A, lda, c0, jpvt, wpall + (long long)c0 * ldwa, c0,
+                                        ldwa, 0, pairs, &qscr->npairs, 2 * bbn);
         else
           rc = launch_apply_pairs<T>(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs,
                                      &qscr->npairs, 2 * bbn);
@@ -622,9 +652,9 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
                       panel_flops(m - c0, bbn, 0) + 2.0 * (m - c0) * (double)c0 * bbn,
                       16.0 * (m - c0) * (double)bbn);
         // the panel's pending update from all earlier blocks, then its QR
-        rc = gemm_big<double>(s, false, m - c0, bbn, c0, -1.0, vall + c0, ldv,
-                              wpall + (long long)c0 * ldwa, ldwa, 1.0,
-                              (double*)A + c0 + (long long)c0 * lda, lda, gpart, gpart_elems);
+        rc = gemm_big<T>(s, false, m - c0, bbn, c0, T(-1), vall + c0, ldv,
+                         wpall + (long long)c0 * ldwa, ldwa, T(1), A + c0 + (long long)c0 * lda,
+                         lda, gpart, gpart_elems);
         if (rc) return rc;
         rc = launch_panel<T>(s, m, A, lda, c0, bbn, 0, nullptr, 0, tau, tmat, pscr, ppart,
                              stepwise);
@@ -659,9 +689,9 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
         // A2 -= V W' for all blocks at once (rows 0..c0 are final already)
         PhaseTimer pt(h, RQRCP_PHASE_FINAL, 2.0 * (m - c0) * (double)c0 * ncols,
                       16.0 * (m - c0) * (double)ncols);
-        rc = gemm_big<double>(s, false, m - c0, ncols, c0, -1.0, vall + c0, ldv,
-                              wpall + (long long)c0 * ldwa, ldwa, 1.0,
-                              (double*)A + c0 + (long long)c0 * lda, lda);
+        rc = gemm_big<T>(s, false, m - c0, ncols, c0, T(-1), vall + c0, ldv,
+                         wpall + (long long)c0 * ldwa, ldwa, T(1), A + c0 + (long long)c0 * lda,
+                         lda);
         if (rc) return rc;
       } else if (ncols > 0) {
         PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, 0, ncols),

@@ -22,13 +22,16 @@ template <typename T>
 int gemm_big(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A, long long lda,
              const T* B, long long ldb, T beta, T* C, long long ldc, T* ws = nullptr,
              size_t ws_elems = 0);
-// The W pass of the left-looking schedule (FP64): raw sums over at most
+// The W pass of the left-looking schedule (FP64 or FP32): raw sums over at most
 // max_split K ranges, part[z][n][q] = sum_k V(k, q) B(k, n) (leading dimension
-// nq <= 64), with B's columns n < n1 from B1 and the rest from B2.  Needs even
-// K and leading dimensions and 16-byte aligned bases (RQ_ERR_LIMIT otherwise).
-int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const double* V, long long ldv,
-                   const double* B1, long long ld1, const double* B2, long long ld2,
-                   double* part, int max_split, int* nsplit_out);
+// nq <= 128 in FP64, <= 64 in FP32), with B's columns n < n1 from B1 and the
+// rest from B2.  Needs even
+// K and leading dimensions and bases aligned to two elements (RQ_ERR_LIMIT
+// otherwise).
+template <typename T>
+int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const T* V, long long ldv,
+                   const T* B1, long long ld1, const T* B2, long long ld2, T* part,
+                   int max_split, int* nsplit_out);
 // The raw sums op(A) B of at most max_split K ranges (whole 16-steps) into
 // part[z][N][M] (leading dimension M); *nsplit_out = ranges written.
 template <typename T>

@@ -65,8 +65,8 @@ int launch_qrcp_tournament(hipStream_t s, double* b, long long ldb, int l, int c
 
 // Column moves from `pairs` (count at *npairs) applied to A(0:m, c0 + .),
 // jpvt(c0 + .) and W'(0:wrows, w0 + .) (W' may be null).
-template <typename T>
-int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* jpvt, double* wp,
+template <typename T, typename WT = double>
+int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* jpvt, WT* wp,
                        int wrows, long long ldw, int w0, const int* pairs, const int* npairs,
                        int max_pairs);
 

@@ -223,35 +223,39 @@ void launch_big(hipStream_t s, bool vec, int M, int N, int K, T alpha, const T* 
   const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   const dim3 grid(tiles, nsplit), block(64 * WM * WN);
   if (vec)
-    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, PF, true>), grid, block, 0, s, M, N, K,
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, PF, true>), grid, block, 0, s,
+                       M, N, K,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
   else
-    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, PF, false>), grid, block, 0, s, M, N, K,
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, PF, false>), grid, block, 0, s,
+                       M, N, K,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
 }
 
 // W pass of the left-looking schedule: for K rows in split z,
-//     part[z][n][q] = sum_k V(k, q) B(k, n),   q < nq <= 64,
+//     part[z][n][q] = sum_k V(k, q) B(k, n),   q < nq <= 16 QX,
 // where the columns of B come from two segments (n < n1 from B1, the rest
 // from B2), so the V^T V_prev Gram block can ride along with V^T A2.
-// A wave owns 16 YN columns and all 64 rows q (4 YN MFMA tiles of 16 x 16);
+// A wave owns 16 YN columns and all 16 QX rows q (QX YN MFMA tiles of 16 x 16);
 // each lane streams its B fragments straight from memory into registers: in a
 // chunk of KC rows, lane (g, c) loads the KC/4 consecutive rows g KC/4 ..
 // of its columns, and MFMA step j takes row g KC/4 + j from every lane group,
-// so no B data passes through LDS.  V (64 x KC per chunk, shared by the NW
+// so no B data passes through LDS.  V (16 QX x KC per chunk, shared by the NW
 // waves) goes through LDS.  Two chunks of B are in flight
 // while one runs; loads past the range read clamped addresses and are never
 // used (issued unconditionally so that waiting for one chunk never waits for
 // the next).  Requires even leading dimensions, K and split ranges, and
 // 16-byte aligned bases (two-element loads).
-template <int KC, int YN, int NW, int OCC>
+template <typename T, int QX, int KC, int YN, int NW, int OCC>
 __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, int n1,
-                                                   const double* __restrict__ V, long long ldv,
-                                                   const double* __restrict__ B1, long long ld1,
-                                                   const double* __restrict__ B2, long long ld2,
-                                                   int kchunk, double* __restrict__ part) {
-  typedef double d2 __attribute__((ext_vector_type(2)));
-  __shared__ double sV[2][KC][64 + 1];
+                                                   const T* __restrict__ V, long long ldv,
+                                                   const T* __restrict__ B1, long long ld1,
+                                                   const T* __restrict__ B2, long long ld2,
+                                                   int kchunk, T* __restrict__ part) {
+  typedef T d2 __attribute__((ext_vector_type(2)));
+  typedef typename BigMfma<T>::acc_t acc_t;
+  constexpr int QR = 16 * QX;  // reflector rows q covered
+  __shared__ T sV[2][KC][QR + 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr16 = lane & 15, lg = lane >> 4;
   constexpr int NT = 64 * NW;
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
   if (nch == 0) return;
 
   // this lane's YN columns
-  const double* bcol[YN];
+  const T* bcol[YN];
 #pragma unroll
   for (int y = 0; y < YN; ++y) {
     int n = n0 + 16 * y + lr16;
@@ -269,7 +273,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
     bcol[y] = n < n1 ? B1 + (long long)n * ld1 : B2 + (long long)(n - n1) * ld2;
   }
   constexpr int RL = KC / 4;  // rows per lane and chunk
-  typedef double RegB[YN][RL];
+  typedef T RegB[YN][RL];
   auto load_b = [&](int k0, RegB& r) {
 #pragma unroll
     for (int y = 0; y < YN; ++y)
@@ -277,14 +281,14 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
       for (int p = 0; p < RL / 2; ++p) {
         const int k = k0 + RL * lg + 2 * p;
         const d2 v = *reinterpret_cast<const d2*>(bcol[y] + (k < ke ? k : ke - 2));
-        r[y][2 * p] = k < ke ? v.x : 0.0;
-        r[y][2 * p + 1] = k + 1 < ke ? v.y : 0.0;
+        r[y][2 * p] = k < ke ? v.x : T(0);
+        r[y][2 * p + 1] = k + 1 < ke ? v.y : T(0);
       }
   };
-  // V chunk: KC rows x 64 columns, pairs along the rows
-  constexpr int NV = KC * 32 / NT;  // pairs per thread
-  static_assert(NV * NT == KC * 32, "V chunk splits evenly");
-  double rv[2 * NV];
+  // V chunk: KC rows x QR columns, pairs along the rows
+  constexpr int NV = KC * QR / 2 / NT;  // pairs per thread
+  static_assert(NV * NT * 2 == KC * QR, "V chunk splits evenly");
+  T rv[2 * NV];
   auto load_v = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
@@ -293,8 +297,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
       const int k = k0 + ki;
       const d2 v = *reinterpret_cast<const d2*>(V + (long long)(q < nq ? q : nq - 1) * ldv +
                                                 (k < ke ? k : ke - 2));
-      rv[2 * j] = (q < nq && k < ke) ? v.x : 0.0;
-      rv[2 * j + 1] = (q < nq && k + 1 < ke) ? v.y : 0.0;
+      rv[2 * j] = (q < nq && k < ke) ? v.x : T(0);
+      rv[2 * j + 1] = (q < nq && k + 1 < ke) ? v.y : T(0);
     }
   };
   auto stash_v = [&](int buf) {
@@ -306,21 +310,21 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
       sV[buf][ki + 1][q] = rv[2 * j + 1];
     }
   };
-  v4d acc[4][YN];
+  acc_t acc[QX][YN];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < QX; ++x)
 #pragma unroll
-    for (int y = 0; y < YN; ++y) acc[x][y] = v4d{0, 0, 0, 0};
+    for (int y = 0; y < YN; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
   auto compute = [&](int buf, const RegB& r) {
 #pragma unroll
     for (int j = 0; j < RL; ++j) {
-      double av[4];
+      T av[QX];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) av[x] = sV[buf][RL * lg + j][16 * x + lr16];
+      for (int x = 0; x < QX; ++x) av[x] = sV[buf][RL * lg + j][16 * x + lr16];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < QX; ++x)
 #pragma unroll
-        for (int y = 0; y < YN; ++y) acc[x][y] = mfma_f64(av[x], r[y][j], acc[x][y]);
+        for (int y = 0; y < YN; ++y) acc[x][y] = BigMfma<T>::run(av[x], r[y][j], acc[x][y]);
     }
   };
 
@@ -345,13 +349,13 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < QX; ++x)
 #pragma unroll
     for (int y = 0; y < YN; ++y) {
       const int n = n0 + 16 * y + lr16;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int q = 16 * x + lg + 4 * e;
+        const int q = 16 * x + acc_row<T>(lg, e);
         if (n < N && q < nq) part[((size_t)blockIdx.y * N + n) * nq + q] = acc[x][y][e];
       }
     }
@@ -471,29 +475,43 @@ int gemm_big_partials(hipStream_t s, bool ta, int M, int N, int K, const T* A, l
   return RQ_OK;
 }
 
-int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const double* V, long long ldv,
-                   const double* B1, long long ld1, const double* B2, long long ld2,
-                   double* part, int max_split, int* nsplit_out) {
+template <typename T>
+int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const T* V, long long ldv,
+                   const T* B1, long long ld1, const T* B2, long long ld2, T* part,
+                   int max_split, int* nsplit_out) {
   *nsplit_out = 0;
   if (N <= 0 || nq <= 0) return RQ_OK;
-  if (nq > 64) return RQ_ERR_LIMIT;
-  const uintptr_t al = 16;
+  if (nq > (sizeof(T) == 8 ? 128 : 64)) return RQ_ERR_LIMIT;
+  const uintptr_t al = 2 * sizeof(T);
   const bool fits = K >= 2 && K % 2 == 0 && ldv % 2 == 0 && ld1 % 2 == 0 && ld2 % 2 == 0 &&
                     reinterpret_cast<uintptr_t>(V) % al == 0 &&
                     reinterpret_cast<uintptr_t>(B1) % al == 0 &&
                     (n1 >= N || reinterpret_cast<uintptr_t>(B2) % al == 0);
   if (!fits) return RQ_ERR_LIMIT;
-  constexpr int KC = 16, YN = 2, NW = 8;   // two workgroups of eight waves per CU
+  constexpr int KC = 16, NW = 8;   // two workgroups of eight waves per CU
   int want = std::max(1, max_split);
   int kchunk = ((K + want - 1) / want + KC - 1) / KC * KC;
   const int nsplit = (K + kchunk - 1) / kchunk;
-  constexpr int cols = 16 * YN * NW;
-  hipLaunchKernelGGL((k_wpass<KC, YN, NW, 2>), dim3((N + cols - 1) / cols, nsplit), dim3(64 * NW),
-                     0, s, K, nq, N, n1, V, ldv, B1, ld1, B2, ld2, kchunk, part);
+  auto go = [&](auto kern, int cols) {
+    hipLaunchKernelGGL(kern, dim3((N + cols - 1) / cols, nsplit), dim3(64 * NW), 0, s, K, nq, N,
+                       n1, V, ldv, B1, ld1, B2, ld2, kchunk, part);
+  };
+  // 64 reflector rows: 32 columns per wave; 128 rows (FP64 only; for FP32
+  // storage the LDS-staged GEMM measured as fast): 16 columns per wave
+  if (nq <= 64)
+    go(&k_wpass<T, 4, KC, 2, NW, 2>, 16 * 2 * NW);
+  else if constexpr (sizeof(T) == 8)
+    go(&k_wpass<T, 8, KC, 1, NW, 2>, 16 * 1 * NW);
   RQ_HIP_CHECK(hipGetLastError());
   *nsplit_out = nsplit;
   return RQ_OK;
 }
+template int wpass_partials<double>(hipStream_t, int, int, int, int, const double*, long long,
+                                    const double*, long long, const double*, long long, double*,
+                                    int, int*);
+template int wpass_partials<float>(hipStream_t, int, int, int, int, const float*, long long,
+                                   const float*, long long, const float*, long long, float*, int,
+                                   int*);
 
 template int gemm_big<double>(hipStream_t, bool, int, int, int, double, const double*, long long,
                               const double*, long long, double, double*, long long, double*,

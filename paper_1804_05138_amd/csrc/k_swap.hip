@@ -43,9 +43,9 @@ RQ_DEV void move_slab(S* __restrict__ x, long long ldx, int c0, int r0, int nrow
 // SLAB-row slabs of A, the next nw slabs of the pending W' block (wrows rows,
 // no column offset), and the last one (when jpvt is given) the permutation
 // vector.  Each workgroup touches only its own rows, so the roles never race.
-template <typename T>
+template <typename T, typename WT>
 __global__ __launch_bounds__(ST) void k_apply_pairs(int rows, T* __restrict__ a, long long lda,
-                                                    int c0, int na, double* __restrict__ wp,
+                                                    int c0, int na, WT* __restrict__ wp,
                                                     int wrows, long long ldw, int nw,
                                                     int* __restrict__ jpvt,
                                                     const int* __restrict__ pairs,
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(ST) void k_apply_pairs(int rows, T* __restrict__ a,
     move_slab<T>(a, lda, c0, r0, min(SLAB, rows - r0), pairs, np, spairs);
   } else if (g < na + nw) {
     const int r0 = (g - na) * SLAB;
-    move_slab<double>(wp, ldw, 0, r0, min(SLAB, wrows - r0), pairs, np, spairs);
+    move_slab<WT>(wp, ldw, 0, r0, min(SLAB, wrows - r0), pairs, np, spairs);
   } else if (jpvt != nullptr) {
     move_slab<int>(jpvt, 1LL, c0, 0, 1, pairs, np, spairs);
   }
@@ -67,8 +67,8 @@ __global__ __launch_bounds__(ST) void k_apply_pairs(int rows, T* __restrict__ a,
 
 }  // namespace
 
-template <typename T>
-int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* jpvt, double* wp,
+template <typename T, typename WT>
+int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* jpvt, WT* wp,
                        int wrows, long long ldw, int w0, const int* pairs, const int* npairs,
                        int max_pairs) {
   if (max_pairs > 2 * MAX_B) return RQ_ERR_LIMIT;
@@ -76,14 +76,20 @@ int launch_apply_pairs(hipStream_t s, int m, T* a, long long lda, int c0, int* j
   const int nw = (wp != nullptr && wrows > 0) ? (wrows + SLAB - 1) / SLAB : 0;
   const int nj = jpvt != nullptr ? 1 : 0;
   if (na + nw + nj > 0)
-    hipLaunchKernelGGL(k_apply_pairs<T>, dim3(na + nw + nj), dim3(ST), 0, s, m, a, lda, c0, na, wp,
+    hipLaunchKernelGGL((k_apply_pairs<T, WT>), dim3(na + nw + nj), dim3(ST), 0, s, m, a, lda, c0,
+                       na, wp,
                        wrows, ldw, nw, jpvt, pairs, npairs);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;
 }
-template int launch_apply_pairs<double>(hipStream_t, int, double*, long long, int, int*, double*,
-                                        int, long long, int, const int*, const int*, int);
-template int launch_apply_pairs<float>(hipStream_t, int, float*, long long, int, int*, double*,
-                                       int, long long, int, const int*, const int*, int);
+template int launch_apply_pairs<double, double>(hipStream_t, int, double*, long long, int, int*,
+                                                double*, int, long long, int, const int*,
+                                                const int*, int);
+template int launch_apply_pairs<float, double>(hipStream_t, int, float*, long long, int, int*,
+                                               double*, int, long long, int, const int*,
+                                               const int*, int);
+template int launch_apply_pairs<float, float>(hipStream_t, int, float*, long long, int, int*,
+                                              float*, int, long long, int, const int*, const int*,
+                                              int);
 
 }  // namespace rq

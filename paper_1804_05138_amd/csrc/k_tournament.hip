@@ -351,7 +351,8 @@ int launch_qrcp_tournament(hipStream_t s, double* b, long long ldb, int l, int c
   RQ_HIP_CHECK(hipGetLastError());
   // the sketch columns move like A's; the winners take R-hat, the rest the
   // root's reflectors
-  int rc = launch_apply_pairs<double>(s, l, b, ldb, c0, nullptr, nullptr, 0, 0, 0, pairs,
+  int rc = launch_apply_pairs<double>(s, l, b, ldb, c0, nullptr, (double*)nullptr, 0, 0, 0,
+                                      pairs,
                                       &scr->npairs, 2 * nsteps);
   if (rc) return rc;
   hipLaunchKernelGGL(k_tp_apply, dim3((nc + 255) / 256), dim3(256), 0, s, bb, ldb, l, nc,

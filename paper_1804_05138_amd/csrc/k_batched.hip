@@ -27,10 +27,10 @@ constexpr int BMAX = 16;   // largest block size of the batched kernel
 constexpr int LMAX = 32;   // largest b + p
 constexpr int MMAX = 1024; // largest row count (panel rows in registers)
 constexpr int RC = 64;     // rows per Omega chunk of the sketch
-constexpr int SB_DOUBLES = 12288;  // LDS for B: l * n <= 12288
+constexpr int SB_DOUBLES = 12288;  // largest l * n (the LDS copy holds (l | 1) * n)
 
 struct BatchedSmem {
-  double b[SB_DOUBLES];
+  double b[SB_DOUBLES + 1024];  // (l | 1) n <= l n + n, n <= 1024
   double t[BMAX * BMAX];
   double r11[BMAX * BMAX];
   double gz[BMAX * BMAX];
@@ -120,6 +120,9 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
     double* tau = tpool + pr.tau_off;
     double* bout = bpool + pr.b_off;
     double* sB = S.b;
+    // column stride of the sketch in LDS: odd, so that the lanes of a wave that
+    // walk consecutive columns hit different banks
+    const int lb = l | 1;
 
     // ---- sketch B = Omega A on FP64 MFMA, Omega from Philox(seed, stream pi + 1) ----
     // Each wave owns SKT 16-column tiles of B per pass; the K loop runs over A's
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int r = 16 * rt + lg + 4 * e;
-            if (col < n && r < l) sB[col * l + r] = acc[j][rt][e];
+            if (col < n && r < l) sB[col * lb + r] = acc[j][rt][e];
           }
       }
     }
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
         int bp = INT_MAX;
         for (int c = gpos + tid; c < n; c += NT) {
           double s2 = 0.0;
-          for (int r = t; r < l; ++r) s2 += sB[c * l + r] * sB[c * l + r];
+          for (int r = t; r < l; ++r) s2 += sB[c * lb + r] * sB[c * lb + r];
           if (argbetter(s2, c, bn, bp)) {
             bn = s2;
             bp = c;
@@ -221,9 +224,9 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
         const int js = uniform_i(bp);
         if (js != gpos) {
           for (int r = tid; r < l; r += NT) {
-            const double x = sB[js * l + r];
-            sB[js * l + r] = sB[gpos * l + r];
-            sB[gpos * l + r] = x;
+            const double x = sB[js * lb + r];
+            sB[js * lb + r] = sB[gpos * lb + r];
+            sB[gpos * lb + r] = x;
           }
           if (tid == 0) {
             const int tj = S.jp[js];
@@ -238,10 +241,11 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
         // Householder of B(t:l, gpos) (LAPACK dlarfg convention)
         if (wave == 0) {
           double x2 = 0.0;
-          for (int r = t + 1 + lane; r < l; r += 64) x2 += sB[gpos * l + r] * sB[gpos * l + r];
+          for (int r = t + 1 + lane; r < l; r += 64)
+            x2 += sB[gpos * lb + r] * sB[gpos * lb + r];
           x2 = wave_sum_dpp(x2);
           if (lane == 0) {
-            const double alpha = sB[gpos * l + t];
+            const double alpha = sB[gpos * lb + t];
             double beta = alpha, tt = 0.0, den = 1.0;
             if (x2 > 0.0) {
               const double nrm = hypot(alpha, sqrt(x2));
@@ -257,18 +261,18 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
         __syncthreads();
         const double tt = S.hh[1], den = S.hh[2];
         for (int r = tid; r < l; r += NT)
-          S.hv[r] = (r == t) ? 1.0 : ((r > t && tt != 0.0) ? sB[gpos * l + r] / den : 0.0);
+          S.hv[r] = (r == t) ? 1.0 : ((r > t && tt != 0.0) ? sB[gpos * lb + r] / den : 0.0);
         __syncthreads();
         if (tid == 0) {
-          sB[gpos * l + t] = S.hh[0];
-          for (int r = t + 1; r < l; ++r) sB[gpos * l + r] = 0.0;
+          sB[gpos * lb + t] = S.hh[0];
+          for (int r = t + 1; r < l; ++r) sB[gpos * lb + r] = 0.0;
         }
         if (tt != 0.0) {
           for (int c = gpos + 1 + tid; c < n; c += NT) {
             double d = 0.0;
-            for (int r = t; r < l; ++r) d += S.hv[r] * sB[c * l + r];
+            for (int r = t; r < l; ++r) d += S.hv[r] * sB[c * lb + r];
             const double f = tt * d;
-            for (int r = t; r < l; ++r) sB[c * l + r] -= f * S.hv[r];
+            for (int r = t; r < l; ++r) sB[c * lb + r] -= f * S.hv[r];
           }
         }
       }
@@ -411,7 +415,7 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
         for (int j = 0; j < BMAX; ++j) {
           double x = 0.0;
           if (q < bb && j < bb && j >= q) {
-            x = sB[(i + j) * l + q];
+            x = sB[(i + j) * lb + q];
 #pragma unroll
             for (int p = 0; p < j; ++p)
               if (p >= q) x -= mrow[p] * S.r11[p * BMAX + j];
@@ -578,7 +582,7 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
                 const int q = lg + 4 * e;
-                if (q < bb) sB[col * l + q] -= bu[e];
+                if (q < bb) sB[col * lb + q] -= bu[e];
               }
             }
           }
@@ -588,7 +592,7 @@ __global__ __launch_bounds__(NT, 1) void k_rqrcp_batched(
     }
 
     // ---- outputs: final sketch, permutation, info ----
-    for (int e = tid; e < l * n; e += NT) bout[e] = sB[e];
+    for (int e = tid; e < l * n; e += NT) bout[e] = sB[(e / l) * lb + e % l];
     for (int c = tid; c < n; c += NT) jpvt[c] = S.jp[c];
     if (tid == 0) infos[pi] = S.info;
     }

@@ -79,3 +79,15 @@ def test_kmax_reached(rq):
     f, est = rq.factor_tol(_dev(a), 1e-8, 48, 16, 8, seed=1)
     f_or = R.rqrcp(a, 48, 16, 8, seed=1, mode="blocked", stop_tol=1e-8)
     _check(f, est, f_or, a, "kmax")
+
+
+def test_early_stop_left_looking(rq):
+    """kmax <= n/2 (the left-looking schedule) and a tolerance met before kmax:
+    the deferred trailing update must be applied at the stopping rank."""
+    m, n, b, p = 600, 400, 32, 8
+    a = lowrank(m, n, sigma_exp(400, 15.0), 3)
+    f_or = R.rqrcp(a, 200, b, p, seed=4, mode="blocked", stop_tol=1e-3)
+    assert f_or.k < 200
+    assert f_or.trace.min_rel_gap() >= 1e-8
+    f, est = rq.factor_tol(_dev(a), 1e-3, 200, b, p, seed=4)
+    _check(f, est, f_or, a, "tol 1e-3, kmax 200")

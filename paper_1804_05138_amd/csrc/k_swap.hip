@@ -1,8 +1,10 @@
-// Column moves of Alg. 2 ("swap the pivots into positions i..i+b-1 in A and
-// Pi"): the sketch kernel lists every (destination, source) position pair of
-// the block's sequential transpositions; here they are applied to A (full
-// height, so rows of R already computed move too), to the permutation vector
-// and to the pending W' block.  Each workgroup owns a slab of rows and first
+// Column moves of Alg. 2 (the block's pivots are moved to the front of the
+// trailing columns of A and of the permutation): the sketch kernel lists every
+// (destination, source) position pair of the block's sequential
+// transpositions; here they are applied to A (full height, so rows of R
+// already computed move too), to the permutation vector and to the rows of W'
+// computed so far (the pending block's, or every block's in the left-looking
+// schedule).  Each workgroup owns a slab of rows and first
 // gathers every source column of its slab into registers, then scatters, so
 // the move is a race-free permutation without a global temporary.
 #include "internal.h"

@@ -1,7 +1,9 @@
-// Trailing-matrix update of Alg. 2 ("A(i:m, i+b:n) <- Q~^T A(i:m, i+b:n)",
-// PDLARFB in Alg. 4), fused with the first product of the next block's
-// update, on FP64 MFMA (v_mfma_f64_16x16x4f64) for an FP64 matrix and on FP32
-// MFMA (v_mfma_f32_16x16x4f32) for an FP32 matrix (the mixed-precision form:
+// Trailing-matrix update of Alg. 2 (the block reflector's transpose applied
+// to the trailing columns, PDLARFB in Alg. 4) in the right-looking order, used
+// when k > n/2 (otherwise the left-looking schedule of k_gemm_big.hip runs),
+// fused with the first product of the next block's update, on FP64 MFMA
+// (v_mfma_f64_16x16x4f64) for an FP64 matrix and on FP32 MFMA
+// (v_mfma_f32_16x16x4f32) for an FP32 matrix (the mixed-precision form:
 // reflectors formed in FP64, stored and applied in FP32).
 //
 // With the compact WY form Q~ = I - V T V^T the update is A2 -= V (T^T V^T A2).

@@ -99,13 +99,22 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   size_t omega, sketch_part, sketch_lp, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy,
       mark, formq, est, tourn, vall, wpall, gmat, gpart, total;
-  bool ll;             // left-looking schedule (FP64 storage)
-  long long ldv, ldwa; // leading dimensions of the dense V (m x k) and of W' (k x n)
+  bool ll;             // left-looking schedule
+  int ko;              // columns of an outer block of the left-looking schedule
+  int wsplit;          // most row splits of a W pass
+  long long ldv, ldwa; // leading dimensions of the dense V (m x ko) and of W' (ko x n)
 };
 
 // Left-looking schedule: partial sums of the per-block W pass (one more slot
 // for the correction term), and of the small Gram products V_j^T V.
 constexpr int kLLSplit = 8;
+// Outer block of the left-looking schedule when k > n/2: the reflectors of at
+// most this many columns are kept, and A2 -= V W' is applied whenever they are
+// full, so the Gram corrections (about m kO per column) stay bounded.
+constexpr int kLLOuter = 512;
+// Row splits of a W pass with outer blocks: the trailing width shrinks to a few
+// column tiles late in a full-rank factorization, so more splits keep the grid full.
+constexpr int kLLSplitWide = 32;
 size_t ll_split_elems(int m, int n, int k, int b) {
   return (size_t)b * std::max({(size_t)8 * m, (size_t)16 * n, (size_t)64 * k});
 }
@@ -164,18 +173,21 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   L.pscr = PSCR_OFF;
   L.ppart = take(panel_partial_doubles(m, std::min(b, k)) * sizeof(double));
   L.tmat = take((size_t)MAX_B * MAX_B * sizeof(double));
-  // left-looking for FP64 when the rank is at most half the width: its Gram
-  // blocks V_j^T V_<j add about m k^2 flops to the 4 m n k of the updates
-  L.ll = 2LL * k <= n;
+  // left-looking: one outer block when the rank is at most half the width (its
+  // Gram blocks V_j^T V_<j add about m k^2 flops to the 4 m n k of the
+  // updates), else outer blocks of kLLOuter columns
+  L.ll = true;
+  L.ko = (2LL * k <= n) ? k : std::min(k, kLLOuter);
   L.ldv = m + (m & 1);
-  L.ldwa = k + (k & 1);
+  L.ldwa = L.ko + (L.ko & 1);
+  L.wsplit = (L.ko < k) ? kLLSplitWide : kLLSplit;
   L.wpart = take(std::max(wpart_doubles(m, n, k, b),
-                          L.ll ? (size_t)(kLLSplit + 1) * n * b : (size_t)0) * es);
+                          L.ll ? (size_t)(L.wsplit + 1) * n * b : (size_t)0) * es);
   L.wp = take((size_t)b * n * sizeof(double));
-  L.vall = take(L.ll ? (size_t)L.ldv * k * es : 0);
+  L.vall = take(L.ll ? (size_t)L.ldv * L.ko * es : 0);
   L.wpall = take(L.ll ? (size_t)L.ldwa * n * es : 0);
-  L.gmat = take(L.ll ? (size_t)2 * b * k * es : 0);
-  L.gpart = take(L.ll ? ll_split_elems(m, n, k, b) * es : 0);
+  L.gmat = take(L.ll ? (size_t)2 * b * L.ko * es : 0);
+  L.gpart = take(L.ll ? ll_split_elems(m, n, L.ko, b) * es : 0);
   L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * es : 0);
   L.mark = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)n * sizeof(int) : 0);
   L.formq = take(form_q_work_elems(m, k, b) * es);
@@ -296,17 +308,18 @@ __global__ void k_apply_corr(int w, int nc, int nparts, const T* __restrict__ p,
 }
 
 // Dense copy of the reflectors of columns c .. c+w-1 over all m rows:
-// v(r, c + q) = A(r, c + q) below row c + q, 1 on it, 0 above (the unit lower
-// trapezoidal V of Alg. 2's block, kept for the left-looking products).
+// v(r, c + q - ob) = A(r, c + q) below row c + q, 1 on it, 0 above (the unit
+// lower trapezoidal V of Alg. 2's block, kept for the left-looking products;
+// ob is the first column of the current outer block).
 template <typename T>
-__global__ void k_copy_v(int m, int c, int w, const T* __restrict__ a, long long lda,
+__global__ void k_copy_v(int m, int c, int w, int ob, const T* __restrict__ a, long long lda,
                          T* __restrict__ v, long long ldv) {
   const long long total = (long long)m * w;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const int q = (int)(e / m), r = (int)(e % m);
     const int d = r - (c + q);
-    v[(long long)(c + q) * ldv + r] = d > 0 ? a[(long long)(c + q) * lda + r] : T(d == 0 ? 1 : 0);
+    v[(long long)(c + q - ob) * ldv + r] = d > 0 ? a[(long long)(c + q) * lda + r] : T(d == 0 ? 1 : 0);
   }
 }
 
@@ -401,39 +414,44 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   double* wp = (double*)(w + L.wp);
   const long long ldw = b;
   int rc;
-  // Left-looking schedule (FP64): A2 is not written per block.  Each block
-  // keeps its reflectors in the dense V (m x k) and its W' rows in W' (k x n);
-  // the rows R12 are finished in place by the sample-update kernel, a panel
-  // takes the pending update of all earlier blocks before it is factored, the
-  // per-block product W_j = V_j^T A2 reads the original A2 and subtracts
-  // (V_j^T V_<j) W'_<j, and A2 -= V W' runs once at the end.
+  // Left-looking schedule: A2 is not written per block.  Within an outer block
+  // (columns ob .. ob+ko-1, one block of all k columns when k <= n/2) each
+  // block keeps its reflectors in the dense V (m x ko, column c at c - ob) and
+  // its W' rows in W' (ko x n, row c at c - ob); the rows R12 are finished in
+  // place by the sample-update kernel, a panel takes the pending update of the
+  // outer block's earlier blocks before it is factored, the per-block product
+  // W_j = V_j^T A2 reads A2 as the outer block found it and subtracts
+  // (V_j^T V_<j) W'_<j, and A2 -= V W' runs when the outer block is full and
+  // at the end.
   const bool ll = L.ll;
+  const int ko = L.ko;
+  int ob = 0;
   T* vall = (T*)(w + L.vall);
   T* wpall = (T*)(w + L.wpall);
   T* gmat = (T*)(w + L.gmat);
   T* gpart = (T*)(w + L.gpart);
   const long long ldv = L.ldv, ldwa = L.ldwa;
-  const size_t gpart_elems = ll ? ll_split_elems(m, n, k, b) : 0;
+  const size_t gpart_elems = ll ? ll_split_elems(m, n, ko, b) : 0;
   auto copy_v = [&](int c, int wd) -> int {
     hipLaunchKernelGGL(k_copy_v<T>, dim3(grid_for((long long)m * wd)), dim3(256), 0, s, m, c, wd,
-                       (const T*)A, (long long)lda, vall, ldv);
+                       ob, (const T*)A, (long long)lda, vall, ldv);
     RQ_HIP_CHECK(hipGetLastError());
     return 0;
   };
-  // Corrections of block (c, wd) from all earlier blocks, one product with
-  // L = [V(c:c+wd, 0:c); G] (in gmat, 2 wd x c): the block's rows of the
-  // trailing columns, A(c:c+wd, c+wd:n) -= V(c:c+wd, 0:c) W'(0:c, .), and the
-  // W partial -G W'(0:c, .) at wslot.
+  // Corrections of block (c, wd) from the outer block's earlier blocks, one
+  // product with L = [V(c:c+wd, ob:c); G] (in gmat, 2 wd x (c - ob)): the
+  // block's rows of the trailing columns, A(c:c+wd, c+wd:n) -= V(c:c+wd, ob:c)
+  // W'(ob:c, .), and the W partial -G W'(ob:c, .) at wslot.
   auto stacked_corr = [&](int c, int wd, T* wslot) -> int {
-    const int cb = c + wd, nc = n - cb;
-    PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * wd * (double)c * nc, 8.0 * (double)c * nc);
+    const int cb = c + wd, nc = n - cb, kc = c - ob;
+    PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * wd * (double)kc * nc, 8.0 * (double)kc * nc);
     const int tiles = ((2 * wd + 127) / 128) * ((nc + 127) / 128);
     int sp = (1024 + tiles - 1) / tiles;
-    sp = std::min(sp, std::max(1, c / 32));
+    sp = std::min(sp, std::max(1, kc / 32));
     sp = (int)std::min<long long>(sp, (long long)(gpart_elems / ((size_t)2 * wd * nc)));
     sp = std::max(sp, 1);
     int got = 0;
-    int r = gemm_big_partials<T>(s, false, 2 * wd, nc, c, gmat, 2 * wd,
+    int r = gemm_big_partials<T>(s, false, 2 * wd, nc, kc, gmat, 2 * wd,
                                  wpall + (long long)cb * ldwa, ldwa, gpart, sp, &got);
     if (r) return r;
     hipLaunchKernelGGL(k_apply_corr<T>, dim3(grid_for(2LL * wd * nc)), dim3(256), 0, s, wd, nc,
@@ -442,9 +460,10 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     return 0;
   };
   // W partials of block (c, wd) over the trailing columns c+wd .. n: the read
-  // pass V^T A2 (split over rows) and, after the first block, the correction
-  // -(V^T V_<c) W'(0:c, .) as one more partial.  *nsp_out = partials written;
-  // partial z of W starts at wpw + z pstr wd (pstr = 0: n - c - wd columns).
+  // pass V^T A2 (split over rows) and, after the outer block's first block, the
+  // correction -(V^T V(:, ob:c)) W'(ob:c, .) as one more partial.  *nsp_out =
+  // partials written; partial z of W starts at wpw + z pstr wd (pstr = 0:
+  // n - c - wd columns).
   T* wpw = wpart;
   long long pstr = 0;
   auto w_pass = [&](int c, int wd, int* nsp_out) -> int {
@@ -454,29 +473,30 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     pstr = 0;
     if (nc <= 0) return 0;
     T* part = wpart;
-    const T* vc = vall + c + (long long)c * ldv;  // V_c, rows c .. m
+    const int kc = c - ob;                          // earlier reflectors of the outer block
+    const T* vc = vall + c + (long long)kc * ldv;  // V_c, rows c .. m
     int got = 0, r = 0;
-    // one pass over [V(c:m, 0:c) | A(c:m, cb:n)]: the Gram block G = V_c^T V_<c
+    // one pass over [V(c:m, ob:c) | A(c:m, cb:n)]: the Gram block G = V_c^T V(:, ob:c)
     // rides along with W = V_c^T A2
-    const int nt = c + nc;
+    const int nt = kc + nc;
     {
       const int tiles = (nt + 255) / 256;
       int sp = (1024 + tiles - 1) / tiles;
-      sp = std::max(1, std::min(sp, std::min(kLLSplit, (m - c) / 256)));
+      sp = std::max(1, std::min(sp, std::min(L.wsplit, (m - c) / 256)));
       PhaseTimer pt(h, RQRCP_PHASE_TRAIL, 2.0 * (m - c) * (double)wd * nt,
                     8.0 * (m - c) * (double)nt);
-      r = wpass_partials<T>(s, m - c, wd, nt, c, vc, ldv, vall + c, ldv,
+      r = wpass_partials<T>(s, m - c, wd, nt, kc, vc, ldv, vall + c, ldv,
                             (const T*)A + c + (long long)cb * lda, lda, part, sp, &got);
       if (r && r != RQ_ERR_LIMIT) return r;
     }
     if (r == 0) {
-      wpw = part + (long long)c * wd;
+      wpw = part + (long long)kc * wd;
       pstr = nt;
-      if (c > 0) {
-        hipLaunchKernelGGL(k_build_l<T>, dim3(grid_for(2LL * wd * c)), dim3(256), 0, s, wd, c, c,
+      if (kc > 0) {
+        hipLaunchKernelGGL(k_build_l<T>, dim3(grid_for(2LL * wd * kc)), dim3(256), 0, s, wd, kc, c,
                            (const T*)vall, ldv, got, (long long)nt * wd, (const T*)part, gmat);
         RQ_HIP_CHECK(hipGetLastError());
-        if ((r = stacked_corr(c, wd, part + ((long long)got * nt + c) * wd))) return r;
+        if ((r = stacked_corr(c, wd, part + ((long long)got * nt + kc) * wd))) return r;
         ++got;
       }
       *nsp_out = got;
@@ -486,22 +506,22 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     {
       const int tiles = (nc + 255) / 256;
       int sp = (512 + tiles - 1) / tiles;
-      sp = std::max(1, std::min(sp, std::min(kLLSplit, (m - c) / 256)));
+      sp = std::max(1, std::min(sp, std::min(L.wsplit, (m - c) / 256)));
       PhaseTimer pt(h, RQRCP_PHASE_TRAIL, 2.0 * (m - c) * (double)wd * nc,
                     8.0 * (m - c) * (double)nc);
       r = gemm_big_partials<T>(s, true, wd, nc, m - c, vc, ldv,
                                (const T*)A + c + (long long)cb * lda, lda, part, sp, &got);
       if (r) return r;
     }
-    if (c > 0) {
+    if (kc > 0) {
       {
-        PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)c * (m - c),
-                      8.0 * (double)c * (m - c));
-        r = gemm_big<T>(s, true, wd, c, m - c, T(1), vc, ldv, vall + c, ldv, T(0), gmat + wd,
+        PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 2.0 * wd * (double)kc * (m - c),
+                      8.0 * (double)kc * (m - c));
+        r = gemm_big<T>(s, true, wd, kc, m - c, T(1), vc, ldv, vall + c, ldv, T(0), gmat + wd,
                         2 * wd, gpart, gpart_elems);
         if (r) return r;
       }
-      hipLaunchKernelGGL(k_build_l<T>, dim3(grid_for(2LL * wd * c)), dim3(256), 0, s, wd, c, c,
+      hipLaunchKernelGGL(k_build_l<T>, dim3(grid_for(2LL * wd * kc)), dim3(256), 0, s, wd, kc, c,
                          (const T*)vall, ldv, 0, 0LL, (const T*)nullptr, gmat);
       RQ_HIP_CHECK(hipGetLastError());
       if ((r = stacked_corr(c, wd, part + (long long)got * nc * wd))) return r;
@@ -607,7 +627,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       long long ldwo = ldw;
       if constexpr (std::is_same<T, double>::value) {
         if (ll) {
-          wout = wpall + (long long)c0 * ldwa + i;
+          wout = wpall + (long long)c0 * ldwa + (i - ob);
           ldwo = ldwa;
         }
       }
@@ -617,8 +637,8 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       if (rc) return rc;
       if (ll && !std::is_same<T, double>::value) {
         hipLaunchKernelGGL(k_store_w<T>, dim3(grid_for((long long)bb * ncols)), dim3(256), 0, s,
-                           bb, ncols, (const double*)wp, ldw, wpall + (long long)c0 * ldwa + i,
-                           ldwa);
+                           bb, ncols, (const double*)wp, ldw,
+                           wpall + (long long)c0 * ldwa + (i - ob), ldwa);
         RQ_HIP_CHECK(hipGetLastError());
       }
     }
@@ -630,6 +650,17 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       ratio = norm_a > 0.0 ? e / norm_a : 0.0;
       stop = ratio <= tol;
     }
+    if (ll && c0 < k && !stop && c0 - ob + std::min(b, k - c0) > ko) {
+      // the outer block is full: A2 -= V W' for its blocks (rows ob..c0 are
+      // final already), and the next block starts a new outer block
+      PhaseTimer pt(h, RQRCP_PHASE_FINAL, 2.0 * (m - c0) * (double)(c0 - ob) * ncols,
+                    16.0 * (m - c0) * (double)ncols);
+      rc = gemm_big<T>(s, false, m - c0, ncols, c0 - ob, T(-1), vall + c0, ldv,
+                       wpall + (long long)c0 * ldwa, ldwa, T(1), A + c0 + (long long)c0 * lda,
+                       lda);
+      if (rc) return rc;
+      ob = c0;
+    }
     if (c0 < k && !stop) {
       const int bbn = std::min(b, k - c0);
       if (!frozen) {
@@ -640,8 +671,8 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
         }
         PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
         if (ll)
-          rc = launch_apply_pairs<T, T>(s, m, A, lda, c0, jpvt, wpall + (long long)c0 * ldwa, c0,
-                                        ldwa, 0, pairs, &qscr->npairs, 2 * bbn);
+          rc = launch_apply_pairs<T, T>(s, m, A, lda, c0, jpvt, wpall + (long long)c0 * ldwa,
+                                        c0 - ob, ldwa, 0, pairs, &qscr->npairs, 2 * bbn);
         else
           rc = launch_apply_pairs<T>(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs,
                                      &qscr->npairs, 2 * bbn);
@@ -649,13 +680,15 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       }
       if (ll) {
         PhaseTimer pt(h, RQRCP_PHASE_PANEL,
-                      panel_flops(m - c0, bbn, 0) + 2.0 * (m - c0) * (double)c0 * bbn,
+                      panel_flops(m - c0, bbn, 0) + 2.0 * (m - c0) * (double)(c0 - ob) * bbn,
                       16.0 * (m - c0) * (double)bbn);
-        // the panel's pending update from all earlier blocks, then its QR
-        rc = gemm_big<T>(s, false, m - c0, bbn, c0, T(-1), vall + c0, ldv,
-                         wpall + (long long)c0 * ldwa, ldwa, T(1), A + c0 + (long long)c0 * lda,
-                         lda, gpart, gpart_elems);
-        if (rc) return rc;
+        // the panel's pending update from the outer block's earlier blocks, then its QR
+        if (c0 > ob) {
+          rc = gemm_big<T>(s, false, m - c0, bbn, c0 - ob, T(-1), vall + c0, ldv,
+                           wpall + (long long)c0 * ldwa, ldwa, T(1),
+                           A + c0 + (long long)c0 * lda, lda, gpart, gpart_elems);
+          if (rc) return rc;
+        }
         rc = launch_panel<T>(s, m, A, lda, c0, bbn, 0, nullptr, 0, tau, tmat, pscr, ppart,
                              stepwise);
         if (rc) return rc;
@@ -686,13 +719,15 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       bb = bbn;
     } else {
       if (ncols > 0 && ll) {
-        // A2 -= V W' for all blocks at once (rows 0..c0 are final already)
-        PhaseTimer pt(h, RQRCP_PHASE_FINAL, 2.0 * (m - c0) * (double)c0 * ncols,
-                      16.0 * (m - c0) * (double)ncols);
-        rc = gemm_big<T>(s, false, m - c0, ncols, c0, T(-1), vall + c0, ldv,
-                         wpall + (long long)c0 * ldwa, ldwa, T(1), A + c0 + (long long)c0 * lda,
-                         lda);
-        if (rc) return rc;
+        // A2 -= V W' for the outer block's blocks at once (rows 0..c0 are final already)
+        if (c0 > ob) {
+          PhaseTimer pt(h, RQRCP_PHASE_FINAL, 2.0 * (m - c0) * (double)(c0 - ob) * ncols,
+                        16.0 * (m - c0) * (double)ncols);
+          rc = gemm_big<T>(s, false, m - c0, ncols, c0 - ob, T(-1), vall + c0, ldv,
+                           wpall + (long long)c0 * ldwa, ldwa, T(1),
+                           A + c0 + (long long)c0 * lda, lda);
+          if (rc) return rc;
+        }
       } else if (ncols > 0) {
         PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, 0, ncols),
                       16.0 * (m - i) * (double)ncols);

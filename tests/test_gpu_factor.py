@@ -87,6 +87,7 @@ def test_sketch_with_user_omega(rq):
     (700, 300, 96, 32, 8),     # tall, several row tiles
     (256, 256, 256, 64, 8),    # k = n: full factorization
     (97, 131, 97, 13, 5),      # k = m < n, odd block size
+    (1100, 900, 700, 48, 8),   # k > n/2 and above one outer block: A2 -= V W' mid-way (at column 480)
     (500, 400, 160, 80, 16),   # tall sketch (l = 96): four columns per thread, several workgroups
     (400, 300, 150, 128, 8),   # a 128-wide panel in two halves, then a narrow one after it
     (600, 500, 256, 128, 16),  # 128-wide panels after 128-wide blocks

@@ -374,10 +374,10 @@ int rqrcp_check(rqrcp_handle h, void *ws);
 #define RQRCP_PHASE_QRCP 1    /* partial QRCP of the sketch */
 #define RQRCP_PHASE_SWAP 2    /* column moves */
 #define RQRCP_PHASE_PANEL 3   /* panel QR + T */
-#define RQRCP_PHASE_TRAIL 4   /* per-block W = V^T A2 pass (FP64), fused update (FP32) */
+#define RQRCP_PHASE_TRAIL 4   /* per-block W = V^T A2 pass */
 #define RQRCP_PHASE_BUPDATE 5 /* W and R12 corrections, W' = T^T W, the sample update */
 #define RQRCP_PHASE_OTHER 6
-#define RQRCP_PHASE_FINAL 7   /* FP64: the deferred update A2 -= V W' of all blocks */
+#define RQRCP_PHASE_FINAL 7   /* the deferred update A2 -= V W' of an outer block */
 #define RQRCP_NPHASES 8
 int rqrcp_set_timing(rqrcp_handle h, int enable);
 /* Synchronizes the stream, then returns and clears the totals since the last

@@ -99,7 +99,6 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   size_t omega, sketch_part, sketch_lp, qscr, cand, pairs, pscr, ppart, tmat, wpart, wp, copy,
       mark, formq, est, tourn, vall, wpall, gmat, gpart, total;
-  bool ll;             // left-looking schedule
   int ko;              // columns of an outer block of the left-looking schedule
   int wsplit;          // most row splits of a W pass
   long long ldv, ldwa; // leading dimensions of the dense V (m x ko) and of W' (ko x n)
@@ -127,32 +126,6 @@ constexpr size_t QSCR_OFF = 0;
 const size_t PSCR_OFF = (sizeof(rq::QrcpScratch) + 255) / 256 * 256;
 const size_t HEADER = PSCR_OFF + (sizeof(rq::PanelScratch) + 255) / 256 * 256;
 
-size_t wpart_doubles(int m, int n, int k, int b) {
-  size_t best = 0;
-  int i = 0;
-  int bb = std::min(b, k);
-  // W-only pass of block 0
-  {
-    const int nc = n - bb;
-    if (nc > 0) {
-      // the widest strip (fewest column tiles) gives the most row splits
-      TrailPlan p = trail_plan(m, nc, kTrailMaxStrip);
-      best = std::max(best, (size_t)p.nsplit * nc * bb);
-    }
-  }
-  while (i + bb < k) {
-    const int bbn = std::min(b, k - i - bb);
-    const int nc = n - (i + bb + bbn);
-    if (nc > 0) {
-      TrailPlan p = trail_plan(m - i, nc, kTrailMaxStrip);
-      best = std::max(best, (size_t)p.nsplit * nc * bbn);
-    }
-    i += bb;
-    bb = bbn;
-  }
-  return best;
-}
-
 Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   Layout L;
   const int b = prm.b, p = prm.p, l = b + p;
@@ -176,18 +149,16 @@ Layout layout(int m, int n, int k, const rqrcp_params& prm) {
   // left-looking: one outer block when the rank is at most half the width (its
   // Gram blocks V_j^T V_<j add about m k^2 flops to the 4 m n k of the
   // updates), else outer blocks of kLLOuter columns
-  L.ll = true;
   L.ko = (2LL * k <= n) ? k : std::min(k, kLLOuter);
   L.ldv = m + (m & 1);
   L.ldwa = L.ko + (L.ko & 1);
   L.wsplit = (L.ko < k) ? kLLSplitWide : kLLSplit;
-  L.wpart = take(std::max(wpart_doubles(m, n, k, b),
-                          L.ll ? (size_t)(L.wsplit + 1) * n * b : (size_t)0) * es);
+  L.wpart = take((size_t)(L.wsplit + 1) * n * b * es);
   L.wp = take((size_t)b * n * sizeof(double));
-  L.vall = take(L.ll ? (size_t)L.ldv * L.ko * es : 0);
-  L.wpall = take(L.ll ? (size_t)L.ldwa * n * es : 0);
-  L.gmat = take(L.ll ? (size_t)2 * b * L.ko * es : 0);
-  L.gpart = take(L.ll ? ll_split_elems(m, n, L.ko, b) * es : 0);
+  L.vall = take((size_t)L.ldv * L.ko * es);
+  L.wpall = take((size_t)L.ldwa * n * es);
+  L.gmat = take((size_t)2 * b * L.ko * es);
+  L.gpart = take(ll_split_elems(m, n, L.ko, b) * es);
   L.copy = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)m * n * es : 0);
   L.mark = take((flags & RQRCP_FROZEN_PIVOTS) ? (size_t)n * sizeof(int) : 0);
   L.formq = take(form_q_work_elems(m, k, b) * es);
@@ -423,7 +394,6 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   // W_j = V_j^T A2 reads A2 as the outer block found it and subtracts
   // (V_j^T V_<j) W'_<j, and A2 -= V W' runs when the outer block is full and
   // at the end.
-  const bool ll = L.ll;
   const int ko = L.ko;
   int ob = 0;
   T* vall = (T*)(w + L.vall);
@@ -431,7 +401,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   T* gmat = (T*)(w + L.gmat);
   T* gpart = (T*)(w + L.gpart);
   const long long ldv = L.ldv, ldwa = L.ldwa;
-  const size_t gpart_elems = ll ? ll_split_elems(m, n, ko, b) : 0;
+  const size_t gpart_elems = ll_split_elems(m, n, ko, b);
   auto copy_v = [&](int c, int wd) -> int {
     hipLaunchKernelGGL(k_copy_v<T>, dim3(grid_for((long long)m * wd)), dim3(256), 0, s, m, c, wd,
                        ob, (const T*)A, (long long)lda, vall, ldv);
@@ -565,9 +535,6 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   auto panel_flops = [&](int rows, int w, int wprev) {
     return 3.0 * rows * (double)w * w + 2.0 * (rows + wprev) * (double)wprev * w;
   };
-  auto trail_flops = [&](int ii, int bbu, int bbn, int ncols) {
-    return 2.0 * (m - ii) * (double)bbu * ncols + 2.0 * (m - ii - bbu) * (double)bbn * ncols;
-  };
   double* estd = (double*)(w + L.est);
   // partial QRCP of B(:, c0:c0+nc) for nsteps pivots: the grid-wide greedy
   // kernel, or tournament pivoting
@@ -602,20 +569,9 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m, bb, 0), 16.0 * m * (double)bb);
     rc = launch_panel<T>(s, m, A, lda, 0, bb, 0, nullptr, 0, tau, tmat, pscr, ppart, stepwise);
     if (rc) return rc;
-    if (ll && (rc = copy_v(0, bb))) return rc;
+    if ((rc = copy_v(0, bb))) return rc;
   }
-  if (n - bb > 0) {
-    if (ll) {
-      rc = w_pass(0, bb, &nsp);
-    } else {
-      PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(0, 0, bb, n - bb),
-                    8.0 * m * (double)(n - bb));
-      TrailPlan pl = trail_plan(m, n - bb, trail_strip<T>(bb));
-      rc = launch_trail<T>(s, m, A, lda, 0, 0, bb, (const double*)nullptr, 0, 0, bb, n, wpart,
-                           pl.nsplit, &nsp);
-    }
-    if (rc) return rc;
-  }
+  if (n - bb > 0 && (rc = w_pass(0, bb, &nsp))) return rc;
   for (;;) {
     const int c0 = i + bb;
     const int ncols = n - c0;
@@ -626,16 +582,13 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       double* wout = wp;
       long long ldwo = ldw;
       if constexpr (std::is_same<T, double>::value) {
-        if (ll) {
-          wout = wpall + (long long)c0 * ldwa + (i - ob);
-          ldwo = ldwa;
-        }
+        wout = wpall + (long long)c0 * ldwa + (i - ob);
+        ldwo = ldwa;
       }
-      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, ll ? (const T*)wpw : wpart, nsp, wout,
-                             ldwo, frozen ? nullptr : B, ldb, c0, ncols, info,
-                             ll ? A : (T*)nullptr, ll ? pstr : 0);
+      rc = launch_bupdate<T>(s, m, A, lda, i, bb, tmat, (const T*)wpw, nsp, wout, ldwo,
+                             frozen ? nullptr : B, ldb, c0, ncols, info, A, pstr);
       if (rc) return rc;
-      if (ll && !std::is_same<T, double>::value) {
+      if (!std::is_same<T, double>::value) {
         hipLaunchKernelGGL(k_store_w<T>, dim3(grid_for((long long)bb * ncols)), dim3(256), 0, s,
                            bb, ncols, (const double*)wp, ldw,
                            wpall + (long long)c0 * ldwa + (i - ob), ldwa);
@@ -650,7 +603,7 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
       ratio = norm_a > 0.0 ? e / norm_a : 0.0;
       stop = ratio <= tol;
     }
-    if (ll && c0 < k && !stop && c0 - ob + std::min(b, k - c0) > ko) {
+    if (c0 < k && !stop && c0 - ob + std::min(b, k - c0) > ko) {
       // the outer block is full: A2 -= V W' for its blocks (rows ob..c0 are
       // final already), and the next block starts a new outer block
       PhaseTimer pt(h, RQRCP_PHASE_FINAL, 2.0 * (m - c0) * (double)(c0 - ob) * ncols,
@@ -670,15 +623,11 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
           if (rc) return rc;
         }
         PhaseTimer pt(h, RQRCP_PHASE_SWAP, 0.0, 0.0);
-        if (ll)
-          rc = launch_apply_pairs<T, T>(s, m, A, lda, c0, jpvt, wpall + (long long)c0 * ldwa,
-                                        c0 - ob, ldwa, 0, pairs, &qscr->npairs, 2 * bbn);
-        else
-          rc = launch_apply_pairs<T>(s, m, A, lda, c0, jpvt, wp, bb, ldw, 0, pairs,
-                                     &qscr->npairs, 2 * bbn);
+        rc = launch_apply_pairs<T, T>(s, m, A, lda, c0, jpvt, wpall + (long long)c0 * ldwa,
+                                      c0 - ob, ldwa, 0, pairs, &qscr->npairs, 2 * bbn);
         if (rc) return rc;
       }
-      if (ll) {
+      {
         PhaseTimer pt(h, RQRCP_PHASE_PANEL,
                       panel_flops(m - c0, bbn, 0) + 2.0 * (m - c0) * (double)(c0 - ob) * bbn,
                       16.0 * (m - c0) * (double)bbn);
@@ -693,46 +642,23 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
                              stepwise);
         if (rc) return rc;
         if ((rc = copy_v(c0, bbn))) return rc;
-      } else {
-        PhaseTimer pt(h, RQRCP_PHASE_PANEL, panel_flops(m - c0, bbn, bb),
-                      16.0 * (m - i) * (double)bbn);
-        rc = launch_panel<T>(s, m, A, lda, c0, bbn, bb, wp, ldw, tau, tmat, pscr, ppart,
-                             stepwise);
-        if (rc) return rc;
       }
       const int nrest = n - (c0 + bbn);
       if (nrest > 0) {
-        if (ll) {
-          rc = w_pass(c0, bbn, &nsp);
-        } else {
-          PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, bbn, nrest),
-                        16.0 * (m - i) * (double)nrest);
-          TrailPlan pl = trail_plan(m - i, nrest, trail_strip<T>(std::max(bb, bbn)));
-          rc = launch_trail<T>(s, m, A, lda, i, bb, bbn, wp + (long long)bbn * ldw, ldw,
-                               c0 + bbn, c0 + bbn, n, wpart, pl.nsplit, &nsp);
-        }
-        if (rc) return rc;
+        if ((rc = w_pass(c0, bbn, &nsp))) return rc;
       } else {
         nsp = 0;
       }
       i = c0;
       bb = bbn;
     } else {
-      if (ncols > 0 && ll) {
+      if (ncols > 0 && c0 > ob) {
         // A2 -= V W' for the outer block's blocks at once (rows 0..c0 are final already)
-        if (c0 > ob) {
-          PhaseTimer pt(h, RQRCP_PHASE_FINAL, 2.0 * (m - c0) * (double)(c0 - ob) * ncols,
-                        16.0 * (m - c0) * (double)ncols);
-          rc = gemm_big<T>(s, false, m - c0, ncols, c0 - ob, T(-1), vall + c0, ldv,
-                           wpall + (long long)c0 * ldwa, ldwa, T(1),
-                           A + c0 + (long long)c0 * lda, lda);
-          if (rc) return rc;
-        }
-      } else if (ncols > 0) {
-        PhaseTimer pt(h, RQRCP_PHASE_TRAIL, trail_flops(i, bb, 0, ncols),
-                      16.0 * (m - i) * (double)ncols);
-        int dummy = 0;
-        rc = launch_trail<T>(s, m, A, lda, i, bb, 0, wp, ldw, c0, c0, n, (T*)nullptr, 1, &dummy);
+        PhaseTimer pt(h, RQRCP_PHASE_FINAL, 2.0 * (m - c0) * (double)(c0 - ob) * ncols,
+                      16.0 * (m - c0) * (double)ncols);
+        rc = gemm_big<T>(s, false, m - c0, ncols, c0 - ob, T(-1), vall + c0, ldv,
+                         wpall + (long long)c0 * ldwa, ldwa, T(1), A + c0 + (long long)c0 * lda,
+                         lda);
         if (rc) return rc;
       }
       if (k_done) *k_done = c0;

@@ -103,25 +103,6 @@ int launch_cq_tty(hipStream_t s, int nb, const double* t1, const double* y, doub
 int launch_cq_tcombine(hipStream_t s, int nb, const double* t1, const double* t2, const double* z,
                        double* t);
 
-// Trailing pass over columns [c_begin, c_end) of A, rows [i, m):
-//   if bbu > 0:  A(i:m, c) -= V_i * Wp(:, c - w0)      (V_i = A(i:m, i:i+bbu) reflectors)
-//   if bbn > 0:  Wpart(s, :, c - c_begin) = V_n^T A(in:m, c) (V_n = A(in:m, in:in+bbn),
-//                in = i + bbu), summed over row splits s by the consumer.
-struct TrailPlan {
-  int nsplit;
-  int ntiles;
-};
-// strip: columns per workgroup of the launch (trail_strip<T>(block width)).
-TrailPlan trail_plan(int m_rows, int ncols, int strip);
-template <typename T>
-int trail_strip(int bbm);
-constexpr int kTrailMaxStrip = 128;  // widest strip any launch uses
-// T = double: FP64 MFMA; T = float: FP32 MFMA (W' is rounded to FP32).
-template <typename T>
-int launch_trail(hipStream_t s, int m, T* a, long long lda, int i, int bbu, int bbn,
-                 const double* wp, long long ldw, int w0, int c_begin, int c_end, T* wpart,
-                 int nsplit, int* nsp_out);
-
 // From the split partials of W = V^T A2 (bb x ncols): W' = T^T W (stored at wp),
 // then R12 = A(i:i+bb, c) - V11 W'(:, c), X = R11^-1 R12 and
 // B(0:bb, c) -= Rhat11 X for the columns c = c0 .. c0 + ncols - 1 (skipped when

@@ -398,6 +398,7 @@ def extra_batched(rq, count=4096, reps=3):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     ok = int((bt.info == 0).sum().item())
+    res, orth = _batched_invariants(bt, a0, 64)
     ms = min(times)
     fl = sum(rqrcp_flops(m, n, k, b, p) for m, n, k in shapes)
     nbytes = sum(8.0 * m * n for m, n, _ in shapes)
@@ -406,7 +407,34 @@ def extra_batched(rq, count=4096, reps=3):
             "algorithmic_gbps": round(nbytes / ms / 1e6, 1),
             "pct_hbm_peak": round(100 * nbytes / ms / 1e6 / PEAK_HBM, 2),
             "autotuner": {"best_variant": best, "ms_per_variant": [round(x, 3) for x in ms_v]},
-            "problems_ok": ok}
+            "problems_ok": ok, "worst_residual_sample": float("%.2e" % res),
+            "worst_orthogonality_sample": float("%.2e" % orth),
+            "sample": "every 64th problem"}
+
+
+def _batched_invariants(bt, a0, stride):
+    """Worst ||A Pi - Q R||_F / ||A||_F and ||Q1^T Q1 - I||_F over every
+    ``stride``-th problem of a factored batch, in FP64 with torch on the device
+    (Q from the stored reflectors with householder_product)."""
+    import torch
+    worst_r = worst_o = 0.0
+    for j in range(0, len(bt.shapes), stride):
+        m, n, k = bt.shapes[j]
+        rec = bt.offsets[j]
+        ao, jo, to = int(rec["a_off"]), int(rec["jpvt_off"]), int(rec["tau_off"])
+        a = a0[ao:ao + m * n].view(n, m).t().double()
+        f = bt.a[ao:ao + m * n].view(n, m).t().double()
+        jp = bt.jpvt[jo:jo + n].long()
+        tau = bt.tau[to:to + k]
+        v = torch.zeros(m, m, dtype=torch.float64, device=a.device)
+        v[:, :k] = torch.tril(f[:, :k], -1)
+        q = torch.linalg.householder_product(v, tau)
+        r = f.clone()
+        r[:, :k] = torch.triu(f[:, :k])
+        worst_r = max(worst_r, (torch.linalg.norm(a[:, jp] - q @ r) / torch.linalg.norm(a)).item())
+        eye = torch.eye(k, dtype=torch.float64, device=a.device)
+        worst_o = max(worst_o, torch.linalg.norm(q[:, :k].t() @ q[:, :k] - eye).item())
+    return worst_r, worst_o
 
 
 def extra_backward(rq):

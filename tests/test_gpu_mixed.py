@@ -108,9 +108,20 @@ def test_fp32_factor_matches_oracle(rq, m, n, k, b, p):
     errs = {"R": _rel(np.triu(af[:k]), np.triu(f_or.a[:k])),
             "V": _rel(np.tril(af[:, :k], -1), np.tril(f_or.a[:, :k], -1)),
             "tau": _rel(_np(f.tau), f_or.tau)}
+    # the factorization's own invariants hold whatever the pivots: A Pi = Q R and
+    # orthonormal Q1, to FP32 accuracy
+    jp = _np(f.jpvt).astype(int)
+    q = R.form_q(af.astype(np.float64), _np(f.tau), m)
+    res = np.linalg.norm(a[:, jp] - q @ R.r_factor(af.astype(np.float64), k)) / np.linalg.norm(a)
+    orth = np.linalg.norm(q[:, :k].T @ q[:, :k] - np.eye(k))
     print((m, n, k, b, p), "min gap %.1e" % gap, "pivots equal", same,
-          {kk: "%.2e" % v for kk, v in errs.items()})
-    if gap >= 1e-3:
+          {kk: "%.2e" % v for kk, v in errs.items()}, "residual %.1e orth %.1e" % (res, orth))
+    assert res <= 2e-5 and orth <= 2e-5
+    # FP32 storage perturbs a trailing sketch norm by about eps32 times the ratio
+    # of the column's first norm to its trailing norm; every decision the oracle
+    # takes with a relative gap of 1e-5 or more must agree (the smallest gap on
+    # these inputs is 1.1e-4)
+    if gap >= 1e-5:
         assert same
     if same:
         for name, e in errs.items():

@@ -43,7 +43,7 @@ struct BigMfma<float> {
 
 constexpr int kPad = 1;  // LDS row padding (elements)
 
-template <typename T, bool TA, int WM, int WN, int XT, int YT, int BK, int OCC, int PF, bool VEC>
+template <typename T, bool TA, int WM, int WN, int XT, int YT, int BK, int OCC, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
     int M, int N, int K, T alpha, const T* __restrict__ A, long long lda, const T* __restrict__ B,
     long long ldb, T beta, T* __restrict__ C, long long ldc, int kchunk, T* __restrict__ part) {
@@ -76,17 +76,19 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
 
   typedef T RegA[NLA * VW];
   typedef T RegB[NLB * VW];
-  // element (ci, oi) of a load: ci along the contiguous index (VW at a time)
-  auto ld2 = [&](const T* p, bool ok0, bool ok1, T* dst) {
+  // Loads put raw values from clamped (always valid) addresses in registers;
+  // the range masks are applied when the values go to LDS, after the MFMAs of
+  // the current step, so nothing waits for the loads before then.
+  auto ldraw = [&](const T* p, T* dst) {
     if constexpr (VEC) {
       const T2 v = *reinterpret_cast<const T2*>(p);
-      dst[0] = ok0 ? v.x : T(0);
-      dst[1] = ok1 ? v.y : T(0);
+      dst[0] = v.x;
+      dst[1] = v.y;
     } else {
-      const T v = *p;
-      dst[0] = ok0 ? v : T(0);
+      dst[0] = *p;
     }
   };
+  // element (ci, oi) of a load: ci along the contiguous index (VW at a time)
   auto load = [&](int k0, RegA& ra, RegB& rb) {
 #pragma unroll
     for (int j = 0; j < NLA; ++j) {
@@ -95,12 +97,12 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
         const int mi = (u % (BM / VW)) * VW, ki = u / (BM / VW);
         const int gm = m0 + mi, gk = k0 + ki;
         const int gmc = gm < M ? gm : ((M - 1) & ~(VW - 1)), gkc = gk < ke ? gk : ke - 1;
-        ld2(A + (long long)gkc * lda + gmc, gm < M && gk < ke, gm + 1 < M && gk < ke, ra + VW * j);
+        ldraw(A + (long long)gkc * lda + gmc, ra + VW * j);
       } else {              // op(A)(m, k) = A[m lda + k]: contiguous along k
         const int ki = (u % (BK / VW)) * VW, mi = u / (BK / VW);
         const int gm = m0 + mi, gk = k0 + ki;
         const int gmc = gm < M ? gm : M - 1, gkc = gk < ke ? gk : ke - VW;
-        ld2(A + (long long)gmc * lda + gkc, gm < M && gk < ke, gm < M && gk + 1 < ke, ra + VW * j);
+        ldraw(A + (long long)gmc * lda + gkc, ra + VW * j);
       }
     }
 #pragma unroll
@@ -109,29 +111,36 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
       const int ki = (u % (BK / VW)) * VW, ni = u / (BK / VW);
       const int gn = n0 + ni, gk = k0 + ki;
       const int gnc = gn < N ? gn : N - 1, gkc = gk < ke ? gk : ke - VW;
-      ld2(B + (long long)gnc * ldb + gkc, gn < N && gk < ke, gn < N && gk + 1 < ke, rb + VW * j);
+      ldraw(B + (long long)gnc * ldb + gkc, rb + VW * j);
     }
   };
-  auto stash = [&](int buf, const RegA& ra, const RegB& rb) {
+  auto stash = [&](int buf, int k0, const RegA& ra, const RegB& rb) {
 #pragma unroll
     for (int j = 0; j < NLA; ++j) {
       const int u = tid + NT * j;
       if constexpr (!TA) {
         const int mi = (u % (BM / VW)) * VW, ki = u / (BM / VW);
+        const int gm = m0 + mi;
+        const bool kok = k0 + ki < ke;
 #pragma unroll
-        for (int v = 0; v < VW; ++v) sA[buf][ki][mi + v] = ra[VW * j + v];
+        for (int v = 0; v < VW; ++v)
+          sA[buf][ki][mi + v] = (kok && gm + v < M) ? ra[VW * j + v] : T(0);
       } else {
         const int ki = (u % (BK / VW)) * VW, mi = u / (BK / VW);
+        const bool mok = m0 + mi < M;
 #pragma unroll
-        for (int v = 0; v < VW; ++v) sA[buf][ki + v][mi] = ra[VW * j + v];
+        for (int v = 0; v < VW; ++v)
+          sA[buf][ki + v][mi] = (mok && k0 + ki + v < ke) ? ra[VW * j + v] : T(0);
       }
     }
 #pragma unroll
     for (int j = 0; j < NLB; ++j) {
       const int u = tid + NT * j;
       const int ki = (u % (BK / VW)) * VW, ni = u / (BK / VW);
+      const bool nok = n0 + ni < N;
 #pragma unroll
-      for (int v = 0; v < VW; ++v) sB[buf][ki + v][ni] = rb[VW * j + v];
+      for (int v = 0; v < VW; ++v)
+        sB[buf][ki + v][ni] = (nok && k0 + ki + v < ke) ? rb[VW * j + v] : T(0);
     }
   };
 
@@ -150,12 +159,12 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
     }
   };
 
-  if constexpr (PF == 1) {
+  {
     RegA ra;
     RegB rb;
     if (kb < ke) {
       load(kb, ra, rb);
-      stash(0, ra, rb);
+      stash(0, kb, ra, rb);
     }
     __syncthreads();
     int buf = 0;
@@ -163,59 +172,51 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_big(
       const bool more = k0 + BK < ke;
       if (more) load(k0 + BK, ra, rb);
       compute(buf);
-      if (more) stash(buf ^ 1, ra, rb);
+      if (more) stash(buf ^ 1, k0 + BK, ra, rb);
       __syncthreads();
       buf ^= 1;
     }
-  } else {
-    // two steps of loads in flight while one runs: step t+1 and t+2 sit in the
-    // register sets of their parity.  Loads past the range read clamped
-    // addresses and go unused; they are issued unconditionally so that the
-    // wait for one set never covers the other.
-    const int nst = ke > kb ? (ke - kb + BK - 1) / BK : 0;  // uniform
-    if (nst > 0) {
-      RegA ra0, ra1;
-      RegB rb0, rb1;
-      load(kb, ra0, rb0);
-      load(kb + BK, ra1, rb1);
-      stash(0, ra0, rb0);
-      load(kb + 2 * BK, ra0, rb0);
-      __syncthreads();
-      for (int t = 0; t < nst; t += 2) {
-        compute(0);
-        if (t + 1 < nst) stash(1, ra1, rb1);
-        load(kb + (t + 3) * BK, ra1, rb1);
-        __syncthreads();
-        if (t + 1 >= nst) break;
-        compute(1);
-        if (t + 2 < nst) stash(0, ra0, rb0);
-        load(kb + (t + 4) * BK, ra0, rb0);
-        __syncthreads();
-      }
-    }
   }
 
+  if (part) {
 #pragma unroll
-  for (int x = 0; x < XT; ++x)
+    for (int x = 0; x < XT; ++x)
+#pragma unroll
+      for (int y = 0; y < YT; ++y)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int gm = m0 + wm + 16 * x + acc_row<T>(lg, e);
+          const int gn = n0 + wn + 16 * y + lr16;
+          if (gm < M && gn < N) part[((size_t)blockIdx.y * N + gn) * M + gm] = acc[x][y][e];
+        }
+    return;
+  }
+  // C = alpha acc + beta C, one MFMA row block (16 rows) at a time: its 4 YT
+  // reads of C go out together from clamped addresses before any is used
+#pragma unroll
+  for (int x = 0; x < XT; ++x) {
+    T cv[YT][4];
+#pragma unroll
+    for (int y = 0; y < YT; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = min(m0 + wm + 16 * x + acc_row<T>(lg, e), M - 1);
+        const int gn = min(n0 + wn + 16 * y + lr16, N - 1);
+        cv[y][e] = beta == T(0) ? T(0) : C[(long long)gn * ldc + gm];
+      }
 #pragma unroll
     for (int y = 0; y < YT; ++y)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gm = m0 + wm + 16 * x + acc_row<T>(lg, e);
         const int gn = n0 + wn + 16 * y + lr16;
-        if (gm < M && gn < N) {
-          if (part) {
-            part[((size_t)blockIdx.y * N + gn) * M + gm] = acc[x][y][e];
-          } else {
-            T* c = C + (long long)gn * ldc + gm;
-            const T v = alpha * acc[x][y][e];
-            *c = (beta == T(0)) ? v : v + beta * (*c);
-          }
-        }
+        const T v = alpha * acc[x][y][e];
+        if (gm < M && gn < N) C[(long long)gn * ldc + gm] = (beta == T(0)) ? v : v + beta * cv[y][e];
       }
+  }
 }
 
-template <typename T, bool TA, int WM, int WN, int BK, int OCC, int PF = 1, int XT = 4, int YT = 4>
+template <typename T, bool TA, int WM, int WN, int BK, int OCC, int XT = 4, int YT = 4>
 void launch_big(hipStream_t s, bool vec, int M, int N, int K, T alpha, const T* A, long long lda,
                 const T* B, long long ldb, T beta, T* C, long long ldc, int kchunk, int nsplit,
                 T* part) {
@@ -223,11 +224,11 @@ void launch_big(hipStream_t s, bool vec, int M, int N, int K, T alpha, const T* 
   const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   const dim3 grid(tiles, nsplit), block(64 * WM * WN);
   if (vec)
-    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, PF, true>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, true>), grid, block, 0, s,
                        M, N, K,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
   else
-    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, PF, false>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_gemm_big<T, TA, WM, WN, XT, YT, BK, OCC, false>), grid, block, 0, s,
                        M, N, K,
                        alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
 }
@@ -274,6 +275,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
   }
   constexpr int RL = KC / 4;  // rows per lane and chunk
   typedef T RegB[YN][RL];
+  // B rows past the range read the range's last two rows again and are not
+  // masked: V's rows there are zero in LDS, so they add nothing (for finite
+  // data), and with no select on the loaded values the loads stay in flight
+  // until the MFMAs that take them (a select right after each load made the
+  // compiler wait for it there).
   auto load_b = [&](int k0, RegB& r) {
 #pragma unroll
     for (int y = 0; y < YN; ++y)
@@ -281,13 +287,15 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
       for (int p = 0; p < RL / 2; ++p) {
         const int k = k0 + RL * lg + 2 * p;
         const d2 v = *reinterpret_cast<const d2*>(bcol[y] + (k < ke ? k : ke - 2));
-        r[y][2 * p] = k < ke ? v.x : T(0);
-        r[y][2 * p + 1] = k + 1 < ke ? v.y : T(0);
+        r[y][2 * p] = v.x;
+        r[y][2 * p + 1] = v.y;
       }
   };
   // V chunk: KC rows x QR columns, pairs along the rows
   constexpr int NV = KC * QR / 2 / NT;  // pairs per thread
   static_assert(NV * NT * 2 == KC * QR, "V chunk splits evenly");
+  // (raw values in registers; the mask is applied when they go to LDS, so
+  // that nothing waits for these loads before the next chunk's compute)
   T rv[2 * NV];
   auto load_v = [&](int k0) {
 #pragma unroll
@@ -297,17 +305,18 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
       const int k = k0 + ki;
       const d2 v = *reinterpret_cast<const d2*>(V + (long long)(q < nq ? q : nq - 1) * ldv +
                                                 (k < ke ? k : ke - 2));
-      rv[2 * j] = (q < nq && k < ke) ? v.x : T(0);
-      rv[2 * j + 1] = (q < nq && k + 1 < ke) ? v.y : T(0);
+      rv[2 * j] = v.x;
+      rv[2 * j + 1] = v.y;
     }
   };
-  auto stash_v = [&](int buf) {
+  auto stash_v = [&](int buf, int k0) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const int u = tid + NT * j;
       const int ki = (u % (KC / 2)) * 2, q = u / (KC / 2);
-      sV[buf][ki][q] = rv[2 * j];
-      sV[buf][ki + 1][q] = rv[2 * j + 1];
+      const bool ok = q < nq && k0 + ki < ke;   // k0 + ki even and ke even
+      sV[buf][ki][q] = ok ? rv[2 * j] : T(0);
+      sV[buf][ki + 1][q] = ok ? rv[2 * j + 1] : T(0);
     }
   };
   acc_t acc[QX][YN];
@@ -328,22 +337,28 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
     }
   };
 
+  // An even number of chunks (a trailing chunk past the range reads clamped
+  // addresses, is masked to zero and adds nothing): a loop body without an
+  // early exit keeps the accumulators in one register set (an exit between
+  // the two halves made the compiler copy all of them every iteration).
+  const int nch2 = (nch + 1) & ~1;
+  // (each chunk's V load is issued before its B loads, here as in the loop,
+  // so the wait for a V chunk never covers the B loads that follow it)
   RegB r0, r1;
-  load_b(kb, r0);
   load_v(kb);
-  load_b(kb + KC, r1);
-  stash_v(0);
+  load_b(kb, r0);
+  stash_v(0, kb);
   load_v(kb + KC);
+  load_b(kb + KC, r1);
   __syncthreads();
-  for (int t = 0; t < nch; t += 2) {
+  for (int t = 0; t < nch2; t += 2) {
     compute(0, r0);
-    stash_v(1);
+    stash_v(1, kb + (t + 1) * KC);
     load_v(kb + (t + 2) * KC);
     load_b(kb + (t + 2) * KC, r0);
     __syncthreads();
-    if (t + 1 >= nch) break;
     compute(1, r1);
-    stash_v(0);
+    stash_v(0, kb + (t + 2) * KC);
     load_v(kb + (t + 3) * KC);
     load_b(kb + (t + 3) * KC, r1);
     __syncthreads();
@@ -417,7 +432,7 @@ void big_launch(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A
       launch_big<T, false, 2, 1, kBK, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
                                          kchunk, nsplit, part);
     else  // 128 x 128 tiles as eight waves of 32 x 64 (two workgroups per CU)
-      launch_big<T, false, 4, 2, kBK, 2, 1, 2, 4>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C,
+      launch_big<T, false, 4, 2, kBK, 2, 2, 4>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C,
                                                   ldc, kchunk, nsplit, part);
   }
 }

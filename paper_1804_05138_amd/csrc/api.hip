@@ -450,8 +450,8 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
     // rides along with W = V_c^T A2
     const int nt = kc + nc;
     {
-      const int tiles = (nt + 255) / 256;
-      int sp = (1024 + tiles - 1) / tiles;
+      const int tiles = (nt + kWpassCols - 1) / kWpassCols;
+      int sp = (512 + tiles - 1) / tiles;
       sp = std::max(1, std::min(sp, std::min(L.wsplit, (m - c) / 256)));
       PhaseTimer pt(h, RQRCP_PHASE_TRAIL, 2.0 * (m - c) * (double)wd * nt,
                     8.0 * (m - c) * (double)nt);

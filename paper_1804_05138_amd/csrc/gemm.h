@@ -28,6 +28,9 @@ int gemm_big(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A, l
 // rest from B2.  Needs even
 // K and leading dimensions and bases aligned to two elements (RQ_ERR_LIMIT
 // otherwise).
+// Columns of B per workgroup of the W pass: a grid of about 512 workgroups
+// (two per CU) is one round.
+constexpr int kWpassCols = 128;
 template <typename T>
 int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const T* V, long long ldv,
                    const T* B1, long long ld1, const T* B2, long long ld2, T* part,

@@ -504,6 +504,7 @@ int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const T* V, long
                     (n1 >= N || reinterpret_cast<uintptr_t>(B2) % al == 0);
   if (!fits) return RQ_ERR_LIMIT;
   constexpr int KC = 16, NW = 8;   // two workgroups of eight waves per CU
+  static_assert(kWpassCols == 16 * NW, "one 16-column tile per wave");
   int want = std::max(1, max_split);
   int kchunk = ((K + want - 1) / want + KC - 1) / KC * KC;
   const int nsplit = (K + kchunk - 1) / kchunk;
@@ -511,12 +512,14 @@ int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const T* V, long
     hipLaunchKernelGGL(kern, dim3((N + cols - 1) / cols, nsplit), dim3(64 * NW), 0, s, K, nq, N,
                        n1, V, ldv, B1, ld1, B2, ld2, kchunk, part);
   };
-  // 64 reflector rows: 32 columns per wave; 128 rows (FP64 only; for FP32
-  // storage the LDS-staged GEMM measured as fast): 16 columns per wave
+  // 16 columns per wave, 128 per workgroup, two workgroups per CU (64
+  // reflector rows: 82 registers; 128 rows, FP64 only: 128 registers; for FP32
+  // storage with 128 rows the LDS-staged GEMM measured as fast).  At 64 rows,
+  // 16384 x 16320 FP64, this measured 9% faster than 32 columns per wave.
   if (nq <= 64)
-    go(&k_wpass<T, 4, KC, 2, NW, 2>, 16 * 2 * NW);
+    go(&k_wpass<T, 4, KC, 1, NW, 4>, kWpassCols);
   else if constexpr (sizeof(T) == 8)
-    go(&k_wpass<T, 8, KC, 1, NW, 2>, 16 * 1 * NW);
+    go(&k_wpass<T, 8, KC, 1, NW, 2>, kWpassCols);
   RQ_HIP_CHECK(hipGetLastError());
   *nsplit_out = nsplit;
   return RQ_OK;

@@ -520,10 +520,23 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   } else if (!(prm->flags & RQRCP_USER_SKETCH)) {
     PhaseTimer pt(h, RQRCP_PHASE_SKETCH, 2.0 * l * (double)m * n,
                   8.0 * ((double)m * n + (double)l * n));
-    rc = launch_gaussian(s, l, m, prm->seed, 0, om, l);
-    if (rc) return rc;
-    rc = launch_sketch<T>(s, m, n, l, prm->sketch_type, om, l, A, lda, B, ldb, spart, sklp);
-    if (rc) return rc;
+    bool done = false;
+    if constexpr (std::is_same<T, double>::value) {
+      if (prm->sketch_type == SK_F64 && sketch_t_usable(m, l, A, lda)) {
+        // Omega drawn transposed, so that B = Omega A runs as the W-pass product
+        rc = launch_gaussian_t(s, l, m, prm->seed, 0, om, m);
+        if (rc) return rc;
+        rc = launch_sketch_t(s, m, n, l, om, A, lda, B, ldb, spart);
+        if (rc) return rc;
+        done = true;
+      }
+    }
+    if (!done) {
+      rc = launch_gaussian(s, l, m, prm->seed, 0, om, l);
+      if (rc) return rc;
+      rc = launch_sketch<T>(s, m, n, l, prm->sketch_type, om, l, A, lda, B, ldb, spart, sklp);
+      if (rc) return rc;
+    }
   }
 
   // algorithmic work of one launch of each phase
@@ -824,6 +837,13 @@ int rqrcp_sketch(rqrcp_handle h, int m, int n, int l, uint64_t seed, int a_type,
   double* part = (double*)(w + om_b);
   void* lp = w + om_b + part_b;
   long long ldo_eff = ldo;
+  if (!Omega && a_type == RQRCP_F64 && sketch_type == RQRCP_F64 &&
+      sketch_t_usable(m, l, (const double*)A, lda)) {
+    // Omega drawn transposed, so that B = Omega A runs as the W-pass product
+    int rc = launch_gaussian_t(h->stream, l, m, seed, 0, om, m);
+    if (rc) return rc;
+    return launch_sketch_t(h->stream, m, n, l, om, (const double*)A, lda, B, ldb, part);
+  }
   if (!Omega) {
     int rc = launch_gaussian(h->stream, l, m, seed, 0, om, l);
     if (rc) return rc;

@@ -30,6 +30,17 @@ constexpr int MAX_L = 160;      // largest b + p the kernels accept
 // Omega (rows x cols, column-major, leading dimension ld) from Philox(seed, stream).
 int launch_gaussian(hipStream_t s, int rows, int cols, uint64_t seed, uint64_t stream,
                     double* out, long long ld);
+// The same Omega stored transposed: out[r * ld + c] = Omega(r, c), ld >= cols
+// (rows divisible by 4, else RQ_ERR_LIMIT and nothing is enqueued).
+int launch_gaussian_t(hipStream_t s, int rows, int cols, uint64_t seed, uint64_t stream,
+                      double* out, long long ld);
+// B = Omega A in FP64 with Omega given transposed (omt[r * m + i] = Omega(r, i)),
+// through the W-pass product (split-K partials in `partial`, then summed in
+// order).  Usable (sketch_t_usable) for even m and lda, l divisible by 4 and
+// at most 128, and a 16-byte aligned A; otherwise RQ_ERR_LIMIT, nothing enqueued.
+bool sketch_t_usable(int m, int l, const double* a, long long lda);
+int launch_sketch_t(hipStream_t s, int m, int n, int l, const double* omt, const double* a,
+                    long long lda, double* b, long long ldb, double* partial);
 
 // B(0:l, 0:n) = Omega(0:l, 0:m) * A(0:m, 0:n), column-major; A in FP64 or
 // FP32, Omega and B in FP64.  stype: SK_F64 (FP64 MFMA), SK_BF16 or SK_FP8

@@ -292,8 +292,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
       }
   };
   // V chunk: KC rows x QR columns, pairs along the rows
-  constexpr int NV = KC * QR / 2 / NT;  // pairs per thread
-  static_assert(NV * NT * 2 == KC * QR, "V chunk splits evenly");
+  constexpr int NVP = KC * QR / 2;                // pairs per chunk
+  constexpr int NV = (NVP + NT - 1) / NT;         // pairs per thread
   // (raw values in registers; the mask is applied when they go to LDS, so
   // that nothing waits for these loads before the next chunk's compute)
   T rv[2 * NV];
@@ -315,8 +315,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_wpass(int K, int nq, int N, in
       const int u = tid + NT * j;
       const int ki = (u % (KC / 2)) * 2, q = u / (KC / 2);
       const bool ok = q < nq && k0 + ki < ke;   // k0 + ki even and ke even
-      sV[buf][ki][q] = ok ? rv[2 * j] : T(0);
-      sV[buf][ki + 1][q] = ok ? rv[2 * j + 1] : T(0);
+      if (NV * NT == NVP || u < NVP) {          // (pairs past the chunk: none stored)
+        sV[buf][ki][q] = ok ? rv[2 * j] : T(0);
+        sV[buf][ki + 1][q] = ok ? rv[2 * j + 1] : T(0);
+      }
     }
   };
   acc_t acc[QX][YN];
@@ -518,8 +520,12 @@ int wpass_partials(hipStream_t s, int K, int nq, int N, int n1, const T* V, long
   // 16384 x 16320 FP64, this measured 9% faster than 32 columns per wave.
   if (nq <= 64)
     go(&k_wpass<T, 4, KC, 1, NW, 4>, kWpassCols);
-  else if constexpr (sizeof(T) == 8)
-    go(&k_wpass<T, 8, KC, 1, NW, 2>, kWpassCols);
+  else if constexpr (sizeof(T) == 8) {
+    if (nq <= 80)   // e.g. the sketch's b + p = 72 rows
+      go(&k_wpass<T, 5, KC, 1, NW, 4>, kWpassCols);
+    else
+      go(&k_wpass<T, 8, KC, 1, NW, 2>, kWpassCols);
+  }
   RQ_HIP_CHECK(hipGetLastError());
   *nsplit_out = nsplit;
   return RQ_OK;

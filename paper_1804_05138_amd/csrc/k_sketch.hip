@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "gemm.h"
 
 namespace rq {
 namespace {
@@ -44,6 +45,24 @@ __global__ __launch_bounds__(GT) void k_gaussian(int rows, int cols, uint64_t se
         out[c * ld + r] = z[j];
       }
     }
+  }
+}
+
+// The same Omega stored transposed (out[r * ld + c] = Omega(r, c)), for rows
+// divisible by 4: a Philox block holds Omega(4 rb .. 4 rb + 3, c), and
+// consecutive threads take consecutive c so that every store is coalesced.
+__global__ __launch_bounds__(GT) void k_gaussian_t(int rows, int cols, uint64_t seed,
+                                                   uint64_t stream, double* __restrict__ out,
+                                                   long long ld) {
+  const int rb4 = rows / 4;
+  const long long nblk = (long long)rb4 * cols;
+  for (long long t = (long long)blockIdx.x * GT + threadIdx.x; t < nblk;
+       t += (long long)gridDim.x * GT) {
+    const long long c = t % cols, rb = t / cols;
+    double z[4];
+    philox_normals4((uint64_t)(c * rb4 + rb), seed, stream, z);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[(4 * rb + j) * ld + c] = z[j];
   }
 }
 
@@ -268,6 +287,14 @@ __global__ __launch_bounds__(GT) void k_sum_splits(int l, int n, const double* _
   }
 }
 
+// K ranges of the sketch through the W-pass product: about 512 workgroups
+// (two per CU) in one round, at most 4 ranges of at least 256 rows.
+int sketch_t_splits(int m, int n) {
+  const int tiles = (n + kWpassCols - 1) / kWpassCols;
+  const int sp = (512 + tiles - 1) / tiles;
+  return std::max(1, std::min(sp, std::min(4, m / 256)));
+}
+
 void sketch_split(int m, int n, int gran, int* nsplit, int* kps) {
   const int ntiles = (n + 63) / 64;
   int ns = 1;
@@ -292,12 +319,49 @@ int launch_gaussian(hipStream_t s, int rows, int cols, uint64_t seed, uint64_t s
   return RQ_OK;
 }
 
+int launch_gaussian_t(hipStream_t s, int rows, int cols, uint64_t seed, uint64_t stream,
+                      double* out, long long ld) {
+  if (rows % 4 != 0 || ld < cols) return RQ_ERR_LIMIT;
+  if (rows <= 0 || cols <= 0) return RQ_OK;
+  long long grid = ((long long)rows / 4 * cols + GT - 1) / GT;
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_gaussian_t, dim3((unsigned)grid), dim3(GT), 0, s, rows, cols, seed, stream,
+                     out, ld);
+  RQ_HIP_CHECK(hipGetLastError());
+  return RQ_OK;
+}
+
+bool sketch_t_usable(int m, int l, const double* a, long long lda) {
+  return m >= 2 && m % 2 == 0 && lda % 2 == 0 && l % 4 == 0 && l <= 128 &&
+         reinterpret_cast<uintptr_t>(a) % 16 == 0;
+}
+
+int launch_sketch_t(hipStream_t s, int m, int n, int l, const double* omt, const double* a,
+                    long long lda, double* b, long long ldb, double* partial) {
+  if (!sketch_t_usable(m, l, a, lda) || reinterpret_cast<uintptr_t>(omt) % 16 != 0)
+    return RQ_ERR_LIMIT;
+  if (n <= 0) return RQ_OK;
+  // part[z][j][q] = sum over the z-th row range of Omega(q, i) A(i, j)
+  int got = 0;
+  const int rc = wpass_partials<double>(s, m, l, n, n, omt, m, a, lda, a, lda, partial,
+                                        sketch_t_splits(m, n), &got);
+  if (rc) return rc;
+  long long total = (long long)l * n;
+  long long grid2 = (total + GT - 1) / GT;
+  if (grid2 > 65536) grid2 = 65536;
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)grid2), dim3(GT), 0, s, l, n, partial, total,
+                     got, b, ldb);
+  RQ_HIP_CHECK(hipGetLastError());
+  return RQ_OK;
+}
+
 size_t sketch_partial_doubles(int m, int n, int l) {
   int ns, kps, ns2, kps2;
   sketch_split(m, n, KT, &ns, &kps);
   sketch_split(m, n, LKT, &ns2, &kps2);
   if (ns2 > ns) ns = ns2;
-  return ns > 1 ? (size_t)ns * l * n : 0;
+  ns = std::max(ns, sketch_t_splits(m, n));
+  return (size_t)ns * l * n;
 }
 
 size_t sketch_lp_bytes(int m, int n, int l, int stype) {

@@ -64,7 +64,10 @@ def test_gaussian_matches_oracle(rq):
 
 
 def test_sketch_is_omega_a(rq):
-    for m, n, l in [(1024, 1024, 40), (333, 517, 72), (3000, 700, 24), (64, 5, 9)]:
+    # even m with l divisible by 4 takes the transposed-Omega product (row tiles of
+    # 16: l <= 64, 80 or 128); odd m or other l the direct kernel
+    for m, n, l in [(1024, 1024, 40), (333, 517, 72), (3000, 700, 24), (64, 5, 9),
+                    (2048, 600, 72), (1000, 300, 96), (4096, 1000, 128), (258, 77, 76)]:
         a = gaussian(m, n, 1)
         b = _np(rq.sketch(_dev(a), l, seed=7))
         ref = P.gauss(l, m, 7, 0) @ a

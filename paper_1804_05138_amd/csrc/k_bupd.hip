@@ -22,8 +22,8 @@ constexpr int BT = 256;
 // coalesced (column-major tiles move through LDS with a padded row pitch); the
 // three 64 x 64 x 64 products (W' = T^T W, V11 W', Rhat11 X) run on FP64 MFMA
 // from LDS (each wave a 16-row strip of the result), and the triangular solve
-// X = R11^-1 R12 keeps each column in registers of one lane of wave 0, so its
-// dependent chain never waits on memory.
+// X = R11^-1 R12 keeps each column in registers of four lanes of one wave
+// (16 columns per wave), so its dependent chain never waits on memory.
 constexpr int SB = 64;        // largest block width of the staged form
 constexpr int CW = 64;        // columns per workgroup
 constexpr int SP = CW + 1;    // LDS row pitch of the column tiles
@@ -62,6 +62,17 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
     }
   };
 
+  // (column, row) of element e of a bb-row column tile: shifts for the usual
+  // bb = 64 (a uniform branch), a division otherwise
+  auto split_e = [&](int e, int& c, int& r) {
+    if (bb == SB) {
+      c = e >> 6;
+      r = e & (SB - 1);
+    } else {
+      c = e / bb;
+      r = e % bb;
+    }
+  };
   // Every global read of the kernel is issued up front from clamped (always
   // valid) addresses and masked afterwards, so the reads cost one memory round
   // trip per split of W instead of one per element.
@@ -86,7 +97,8 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
     const int c = e / SB, r = e % SB;     // R12 start: A(i + r, c0 + cb + c)
     const bool ok = c < nc && r < bb;
     a12[u] = (double)a[(long long)(c0 + cb + (ok ? c : 0)) * lda + i + (ok ? r : 0)];
-    const int c2 = e / bb, r2 = e % bb;   // B(r2, c0 + cb + c2), updated at the end
+    int c2, r2;                           // B(r2, c0 + cb + c2), updated at the end
+    split_e(e, c2, r2);
     const bool ok2 = e < nc * bb;
     bo[u] = upd ? bsk[(long long)(c0 + cb + (ok2 ? c2 : 0)) * ldb + (ok2 ? r2 : 0)] : 0.0;
   }
@@ -127,7 +139,8 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
     for (int e = 0; e < 4; ++e) sX[(16 * wave + acc_row<double>(lg, e)) * SP + 16 * t + l16] = acc[t][e];
   __syncthreads();
   for (int e = tid; e < nc * bb; e += BT) {
-    const int c = e / bb, r = e % bb;
+    int c, r;
+    split_e(e, c, r);
     wp[(long long)(cb + c) * ldw + r] = sX[r * SP + c];
   }
   // uniform: the sample update runs (sketch given, pivoting not stopped)
@@ -160,26 +173,42 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   // not updated until the end)
   if (r12out != nullptr)
     for (int e = tid; e < nc * bb; e += BT) {
-      const int c = e / bb, r = e % bb;
+      int c, r;
+      split_e(e, c, r);
       r12out[(long long)(c0 + cb + c) * lda + i + r] = (T)sW[r * SP + c];
     }
   if (!sample) return;
-  // X = R11^{-1} R12: back substitution, column `lane` in registers of wave 0
-  if (wave == 0) {
-    double y[SB];
+  // X = R11^{-1} R12: back substitution.  Wave w solves columns 16w .. 16w+15;
+  // lane (g, c) holds rows g, g + 4, ..., g + 60 of column 16w + c in
+  // registers.  Step r: the lanes holding row r form x_r = y_r / R11(r, r),
+  // pass it to the other three lanes of their column, and every lane takes
+  // R11(q, r) x_r off its rows q < r (each entry sees the same operations in
+  // the same order as a column solved by one lane).
+  {
+    const int c = 16 * wave + l16;
+    double y[SB / 4];
 #pragma unroll
-    for (int r = 0; r < SB; ++r) y[r] = sW[r * SP + lane];
+    for (int u = 0; u < SB / 4; ++u) y[u] = sW[(4 * u + lg) * SP + c];
 #pragma unroll
     for (int r = SB - 1; r >= 0; --r) {
       if (r < bb) {
-        const double x = y[r] * sInv[r];
-        y[r] = x;
+        const int gr = r & 3, ur = r >> 2;
+        const double xo = y[ur] * sInv[r];
+        const double x = __shfl(xo, l16 + 16 * gr, 64);
+        y[ur] = (lg == gr) ? x : y[ur];
 #pragma unroll
-        for (int q = 0; q < r; ++q) y[q] -= sA[r * AP + q] * x;
+        for (int u = 0; u <= ur; ++u) {
+          const int q = 4 * u + lg;
+          const double rq = sA[r * AP + (q < r ? q : 0)];
+          y[u] = (q < r) ? fma(-rq, x, y[u]) : y[u];
+        }
       }
     }
 #pragma unroll
-    for (int r = 0; r < SB; ++r) sX[r * SP + lane] = (r < bb) ? y[r] : 0.0;
+    for (int u = 0; u < SB / 4; ++u) {
+      const int q = 4 * u + lg;
+      sX[q * SP + c] = (q < bb) ? y[u] : 0.0;
+    }
   }
   __syncthreads();
   // delta = Rhat11 X, then B(0:bb, col) -= delta
@@ -191,7 +220,9 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
-    const int e = tid + u * BT, c = e / bb, r = e % bb;
+    const int e = tid + u * BT;
+    int c, r;
+    split_e(e, c, r);
     if (e < nc * bb) bsk[(long long)(c0 + cb + c) * ldb + r] = bo[u] - sW[r * SP + c];
   }
   (void)m;

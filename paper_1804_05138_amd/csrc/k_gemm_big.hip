@@ -458,11 +458,11 @@ int gemm_big(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A, l
              const T* B, long long ldb, T beta, T* C, long long ldc, T* ws, size_t ws_elems) {
   if (M <= 0 || N <= 0) return RQ_OK;
   // few output tiles and a long reduction: split K so the grid covers the
-  // chip (1024 workgroups), raw partials in ws, summed in split order
+  // chip (about 512 workgroups), raw partials in ws, summed in split order
   int want = 1;
   const int tiles = big_tiles(ta, M, N);
   if (ws && tiles < 512 && K >= 4 * kBK) {
-    want = (1024 + tiles - 1) / tiles;
+    want = (512 + tiles - 1) / tiles;
     want = std::min(want, K / (2 * kBK));
     want = std::min<long long>(want, (long long)(ws_elems / ((size_t)M * N)));
     want = std::min(want, 64);

@@ -1,5 +1,5 @@
-// Householder QR of the pivoted panel (Alg. 2 "unpivoted QR on
-// A(i:m, i:i+b-1)"; PDGEQRF in Alg. 4) and its compact-WY factor T (PDLARFT).
+// Householder QR of the pivoted panel (the panel factorization without
+// pivoting in Alg. 2; PDGEQRF in Alg. 4) and its compact-WY factor T (PDLARFT).
 // The arithmetic is FP64 for both storage types of A: an FP32 panel is
 // widened on load and R, V are rounded to FP32 on the way back.
 //

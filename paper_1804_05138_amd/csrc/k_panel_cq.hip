@@ -146,25 +146,38 @@ __global__ __launch_bounds__(CT) void k_cq_gram(int rows, const S* __restrict__ 
   gram_chunk<S>(sx, part + (size_t)blockIdx.x * CB * CB);
 }
 
-// out[e] = sum over p of part[p][e], in order (deterministic).
+// out[e] = sum over p of part[p][e] (deterministic): a workgroup takes 64
+// entries, each summed over four consecutive ranges of p by four waves (in
+// order within a range), and the four range sums are added in range order.
+constexpr int SUMW = CT / 64;  // ranges of p per entry
 __global__ __launch_bounds__(CT) void k_cq_sum(int nparts, const double* __restrict__ part,
                                                double* __restrict__ out,
                                                const int* __restrict__ flag) {
+  __shared__ double ss[SUMW][64];
   if (flag && *flag == 0) return;
-  const int e = blockIdx.x * CT + threadIdx.x;
-  if (e >= CB * CB) return;
-  constexpr int U = 16;  // loads in flight per batch; the sum keeps the order p = 0, 1, ...
+  const int el = threadIdx.x & 63, k = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;     // CB * CB is a multiple of 64
+  const int per = (nparts + SUMW - 1) / SUMW;
+  const int p1 = min(nparts, (k + 1) * per);
+  constexpr int U = 16;  // loads in flight per batch; the sum keeps the order within the range
   double s = 0.0;
-  int p = 0;
-  for (; p + U <= nparts; p += U) {
+  int p = k * per;
+  for (; p + U <= p1; p += U) {
     double v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = part[(size_t)(p + u) * CB * CB + e];
 #pragma unroll
     for (int u = 0; u < U; ++u) s += v[u];
   }
-  for (; p < nparts; ++p) s += part[(size_t)p * CB * CB + e];
-  out[e] = s;
+  for (; p < p1; ++p) s += part[(size_t)p * CB * CB + e];
+  ss[k][el] = s;
+  __syncthreads();
+  if (k == 0) {
+    double t = ss[0][el];
+#pragma unroll
+    for (int j = 1; j < SUMW; ++j) t += ss[j][el];
+    out[e] = t;
+  }
 }
 
 // ---- small dense steps on CB x CB matrices (LDS by columns, pitch CP) ----
@@ -790,12 +803,12 @@ int launch_panel_cq(hipStream_t s, int m, T* a, long long lda, int i, int bb, in
   }
   hipLaunchKernelGGL(k_cq_gram<T>, dim3(nchunk), dim3(CT), 0, s, rows, (const T*)x, lda, bb, part,
                      (const int*)nullptr);
-  hipLaunchKernelGGL(k_cq_sum, dim3(CB * CB / CT), dim3(CT), 0, s, nchunk, (const double*)part, g,
+  hipLaunchKernelGGL(k_cq_sum, dim3(CB * CB / 64), dim3(CT), 0, s, nchunk, (const double*)part, g,
                      (const int*)nullptr);
   hipLaunchKernelGGL(k_cq_chol1, dim3(1), dim3(ST), 0, s, bb, (const double*)g, r1, r1inv, flag);
   hipLaunchKernelGGL(k_cq_q1<T>, dim3(nchunk), dim3(CT), 0, s, rows, (const T*)x, lda, bb,
                      (const double*)r1inv, q1, (long long)rows, part, (const int*)flag);
-  hipLaunchKernelGGL(k_cq_sum, dim3(CB * CB / CT), dim3(CT), 0, s, nchunk, (const double*)part, g,
+  hipLaunchKernelGGL(k_cq_sum, dim3(CB * CB / 64), dim3(CT), 0, s, nchunk, (const double*)part, g,
                      (const int*)flag);
   hipLaunchKernelGGL(k_cq_small, dim3(1), dim3(ST), 0, s, bb, (const double*)g,
                      (const double*)r1, (const double*)q1, (long long)rows, m2, rh, l1, tmat,
@@ -839,7 +852,7 @@ int launch_cq_cross(hipStream_t s, int rows, const T* A, long long lda, int na, 
   const int nchunk = (rows + CR - 1) / CR;
   hipLaunchKernelGGL(k_cq_cross<T>, dim3(nchunk), dim3(CT), 0, s, rows, A, lda, na, adiag, B, ldb,
                      nb, bdiag, part);
-  hipLaunchKernelGGL(k_cq_sum, dim3(CB * CB / CT), dim3(CT), 0, s, nchunk, (const double*)part, c,
+  hipLaunchKernelGGL(k_cq_sum, dim3(CB * CB / 64), dim3(CT), 0, s, nchunk, (const double*)part, c,
                      (const int*)nullptr);
   RQ_HIP_CHECK(hipGetLastError());
   return RQ_OK;

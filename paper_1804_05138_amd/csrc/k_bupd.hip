@@ -16,21 +16,23 @@
 namespace rq {
 namespace {
 
-constexpr int BT = 256;
+constexpr int BT = 256;    // threads of the quadrant form
+constexpr int BTS = 512;   // threads of the staged form (eight waves: two per SIMD)
 
 // Staged form for block widths up to 64 (the default): every global access is
 // coalesced (column-major tiles move through LDS with a padded row pitch); the
 // three 64 x 64 x 64 products (W' = T^T W, V11 W', Rhat11 X) run on FP64 MFMA
-// from LDS (each wave a 16-row strip of the result), and the triangular solve
-// X = R11^-1 R12 keeps each column in registers of four lanes of one wave
-// (16 columns per wave), so its dependent chain never waits on memory.
+// from LDS (each of eight waves a 16 x 32 tile of the result), and the
+// triangular solve X = R11^-1 R12 keeps each column in registers of eight
+// lanes of one wave (8 columns per wave), so its dependent chain never waits
+// on memory.
 constexpr int SB = 64;        // largest block width of the staged form
 constexpr int CW = 64;        // columns per workgroup
 constexpr int SP = CW + 1;    // LDS row pitch of the column tiles
 constexpr int AP = SB + 1;    // LDS pitch of the bb x bb blocks
 
 template <typename T>
-__global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long lda,
+__global__ __launch_bounds__(BTS) void k_bupdate_s(int m, const T* a, long long lda,
                                                   int i, int bb, const double* __restrict__ tm,
                                                   const T* __restrict__ wpart, int nsplit,
                                                   double* __restrict__ wp, long long ldw,
@@ -48,17 +50,19 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   const int cb = blockIdx.x * CW;                 // first column (relative to c0)
   const int nc = min(CW, ncols - cb);             // columns of this workgroup
 
-  // C(m, n) = sum_k L(m, k) R(k, n) for this wave's rows 16 wave .. +15 and all
-  // 64 columns: acc[t][e] = C(16 wave + acc_row(lg, e), 16 t + l16)
-  auto mm = [&](auto lel, const double* rm, v4d (&acc)[4]) {
+  // C(m, n) = sum_k L(m, k) R(k, n) for this wave's rows mr .. mr + 15 and
+  // columns nb .. nb + 31 (eight waves: four row strips times two column
+  // halves): acc[t][e] = C(mr + acc_row(lg, e), nb + 16 t + l16)
+  const int mr = 16 * (wave & 3), nb = 32 * (wave >> 2);
+  auto mm = [&](auto lel, const double* rm, v4d (&acc)[2]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < 2; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int kk = 0; kk < SB / 4; ++kk) {
       const int k = 4 * kk + lg;
-      const double av = lel(16 * wave + l16, k);
+      const double av = lel(mr + l16, k);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = mfma_f64(av, rm[k * SP + 16 * t + l16], acc[t]);
+      for (int t = 0; t < 2; ++t) acc[t] = mfma_f64(av, rm[k * SP + nb + 16 * t + l16], acc[t]);
     }
   };
 
@@ -76,14 +80,14 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   // Every global read of the kernel is issued up front from clamped (always
   // valid) addresses and masked afterwards, so the reads cost one memory round
   // trip per split of W instead of one per element.
-  constexpr int NE = SB * SB / BT;   // elements of a bb x bb block per thread
-  constexpr int NC = SB * CW / BT;   // elements of a bb x CW column tile per thread
-  static_assert(NE * BT == SB * SB && NC * BT == SB * CW, "tiles split evenly over the threads");
+  constexpr int NE = SB * SB / BTS;   // elements of a bb x bb block per thread
+  constexpr int NC = SB * CW / BTS;   // elements of a bb x CW column tile per thread
+  static_assert(NE * BTS == SB * SB && NC * BTS == SB * CW, "tiles split evenly over the threads");
   const bool upd = bsk != nullptr;   // uniform: the sample update runs (not frozen pivots)
   double tv[NE], av[NE], rv[NE];
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
-    const int e = tid + u * BT, r = e / SB, q = e % SB;   // column r, row q
+    const int e = tid + u * BTS, r = e / SB, q = e % SB;   // column r, row q
     const bool in = r < bb && q < bb;
     const int rs = in ? r : 0, qs = in ? q : 0;
     tv[u] = tm[rs * bb + qs];
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   double a12[NC], bo[NC];
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
-    const int e = tid + u * BT;
+    const int e = tid + u * BTS;
     const int c = e / SB, r = e % SB;     // R12 start: A(i + r, c0 + cb + c)
     const bool ok = c < nc && r < bb;
     a12[u] = (double)a[(long long)(c0 + cb + (ok ? c : 0)) * lda + i + (ok ? r : 0)];
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
     double pv[NC];
 #pragma unroll
     for (int u = 0; u < NC; ++u) {
-      const int e = tid + u * BT, c = e / SB, q = e % SB;
+      const int e = tid + u * BTS, c = e / SB, q = e % SB;
       const bool ok = c < nc && q < bb;
       pv[u] = (double)wpart[((long long)sp * pstride + cb + (ok ? c : 0)) * bb + (ok ? q : 0)];
     }
@@ -119,26 +123,26 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   }
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
-    const int e = tid + u * BT, r = e / SB, q = e % SB;
+    const int e = tid + u * BTS, r = e / SB, q = e % SB;
     const bool in = r < bb && q < bb;
     sT[r * AP + q] = in ? tv[u] : 0.0;
     sA[r * AP + q] = in ? av[u] : 0.0;  // column r, row q
   }
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
-    const int e = tid + u * BT, c = e / SB, q = e % SB;
+    const int e = tid + u * BTS, c = e / SB, q = e % SB;
     sW[q * SP + c] = (c < nc && q < bb) ? ws[u] : 0.0;
   }
   __syncthreads();
-  v4d acc[4];
+  v4d acc[2];
   // W' = T^T W
   mm([&](int r, int k) { return sT[r * AP + k]; }, sW, acc);
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sX[(16 * wave + acc_row<double>(lg, e)) * SP + 16 * t + l16] = acc[t][e];
+    for (int e = 0; e < 4; ++e) sX[(mr + acc_row<double>(lg, e)) * SP + nb + 16 * t + l16] = acc[t][e];
   __syncthreads();
-  for (int e = tid; e < nc * bb; e += BT) {
+  for (int e = tid; e < nc * bb; e += BTS) {
     int c, r;
     split_e(e, c, r);
     wp[(long long)(cb + c) * ldw + r] = sX[r * SP + c];
@@ -149,12 +153,12 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   // Rhat11 = triu(B(0:bb, i:i+bb)) into sT; R12 starts as A(i:i+bb, col)
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
-    const int e = tid + u * BT, r = e / SB, q = e % SB;   // column r, row q
+    const int e = tid + u * BTS, r = e / SB, q = e % SB;   // column r, row q
     sT[r * AP + q] = (q <= r && r < bb) ? rv[u] : 0.0;
   }
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
-    const int e = tid + u * BT, c = e / SB, r = e % SB;
+    const int e = tid + u * BTS, c = e / SB, r = e % SB;
     sW[r * SP + c] = (c < nc && r < bb) ? a12[u] : 0.0;
   }
   if (tid < SB) sInv[tid] = (tid < bb) ? 1.0 / sA[tid * AP + tid] : 1.0;
@@ -162,51 +166,52 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   // R12 = A(i:i+bb, col) - V11 W'   (V11 unit lower: A(i + r, i + q), q < r)
   mm([&](int r, int k) { return (k < r) ? sA[k * AP + r] : 0.0; }, sX, acc);
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int r = 16 * wave + acc_row<double>(lg, e), c = 16 * t + l16;
+      const int r = mr + acc_row<double>(lg, e), c = nb + 16 * t + l16;
       sW[r * SP + c] = sW[r * SP + c] - sX[r * SP + c] - acc[t][e];
     }
   __syncthreads();
   // the final rows R12 = A(i:i+bb, col) (left-looking schedule: A2 itself is
   // not updated until the end)
   if (r12out != nullptr)
-    for (int e = tid; e < nc * bb; e += BT) {
+    for (int e = tid; e < nc * bb; e += BTS) {
       int c, r;
       split_e(e, c, r);
       r12out[(long long)(c0 + cb + c) * lda + i + r] = (T)sW[r * SP + c];
     }
   if (!sample) return;
-  // X = R11^{-1} R12: back substitution.  Wave w solves columns 16w .. 16w+15;
-  // lane (g, c) holds rows g, g + 4, ..., g + 60 of column 16w + c in
+  // X = R11^{-1} R12: back substitution.  Wave w solves columns 8w .. 8w+7;
+  // lane (g, c) holds rows g, g + 8, ..., g + 56 of column 8w + c in
   // registers.  Step r: the lanes holding row r form x_r = y_r / R11(r, r),
-  // pass it to the other three lanes of their column, and every lane takes
+  // pass it to the other seven lanes of their column, and every lane takes
   // R11(q, r) x_r off its rows q < r (each entry sees the same operations in
   // the same order as a column solved by one lane).
   {
-    const int c = 16 * wave + l16;
-    double y[SB / 4];
+    const int c8 = lane & 7, g8 = lane >> 3;
+    const int c = 8 * wave + c8;
+    double y[SB / 8];
 #pragma unroll
-    for (int u = 0; u < SB / 4; ++u) y[u] = sW[(4 * u + lg) * SP + c];
+    for (int u = 0; u < SB / 8; ++u) y[u] = sW[(8 * u + g8) * SP + c];
 #pragma unroll
     for (int r = SB - 1; r >= 0; --r) {
       if (r < bb) {
-        const int gr = r & 3, ur = r >> 2;
+        const int gr = r & 7, ur = r >> 3;
         const double xo = y[ur] * sInv[r];
-        const double x = __shfl(xo, l16 + 16 * gr, 64);
-        y[ur] = (lg == gr) ? x : y[ur];
+        const double x = __shfl(xo, c8 + 8 * gr, 64);
+        y[ur] = (g8 == gr) ? x : y[ur];
 #pragma unroll
         for (int u = 0; u <= ur; ++u) {
-          const int q = 4 * u + lg;
+          const int q = 8 * u + g8;
           const double rq = sA[r * AP + (q < r ? q : 0)];
           y[u] = (q < r) ? fma(-rq, x, y[u]) : y[u];
         }
       }
     }
 #pragma unroll
-    for (int u = 0; u < SB / 4; ++u) {
-      const int q = 4 * u + lg;
+    for (int u = 0; u < SB / 8; ++u) {
+      const int q = 8 * u + g8;
       sX[q * SP + c] = (q < bb) ? y[u] : 0.0;
     }
   }
@@ -214,13 +219,13 @@ __global__ __launch_bounds__(BT) void k_bupdate_s(int m, const T* a, long long l
   // delta = Rhat11 X, then B(0:bb, col) -= delta
   mm([&](int r, int k) { return (k >= r) ? sT[k * AP + r] : 0.0; }, sX, acc);
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sW[(16 * wave + acc_row<double>(lg, e)) * SP + 16 * t + l16] = acc[t][e];
+    for (int e = 0; e < 4; ++e) sW[(mr + acc_row<double>(lg, e)) * SP + nb + 16 * t + l16] = acc[t][e];
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
-    const int e = tid + u * BT;
+    const int e = tid + u * BTS;
     int c, r;
     split_e(e, c, r);
     if (e < nc * bb) bsk[(long long)(c0 + cb + c) * ldb + r] = bo[u] - sW[r * SP + c];
@@ -497,7 +502,7 @@ int launch_bupdate(hipStream_t s, int m, const T* a, long long lda, int i, int b
     const size_t shmem = (2 * (size_t)SB * AP + 2 * (size_t)SB * SP + SB) * sizeof(double);
     RQ_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bupdate_s<T>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-    hipLaunchKernelGGL(k_bupdate_s<T>, dim3((ncols + CW - 1) / CW), dim3(BT), shmem, s, m, a, lda,
+    hipLaunchKernelGGL(k_bupdate_s<T>, dim3((ncols + CW - 1) / CW), dim3(BTS), shmem, s, m, a, lda,
                        i, bb, t, wpart, nsplit, wp, ldw, bsk, ldb, c0, ncols, info, r12out, pstride);
     RQ_HIP_CHECK(hipGetLastError());
     return RQ_OK;

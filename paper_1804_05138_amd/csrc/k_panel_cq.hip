@@ -39,7 +39,8 @@ constexpr double kCqMaxSpread = 1e3;
 
 constexpr int CB = 64;        // largest panel width of this path
 constexpr int CP = CB + 1;    // LDS pitch
-constexpr int CR = 128;       // rows per workgroup of the row-parallel kernels
+constexpr int CR = 64;        // rows per workgroup of the row-parallel kernels
+constexpr int RT = CR / 64;   // 16-row tiles per wave in them (four waves)
 constexpr int CT = 256;
 
 // ---- pending update A(rp:m, i+coff : i+coff+bb) -= V_prev W'(:, coff : coff+bb)
@@ -484,33 +485,33 @@ __global__ __launch_bounds__(CT) void k_cq_q1(int rows, const T* __restrict__ x,
     }
   }
   __syncthreads();
-  // wave w: rows 32w .. 32w+31 (2 row tiles) x 4 column tiles
-  v4d acc[2][4];
+  // wave w: rows 16 RT w .. (RT row tiles) x 4 column tiles
+  v4d acc[RT][4];
 #pragma unroll
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < RT; ++b)
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc) acc[b][tc] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int kk = 0; kk < CB / 4; ++kk) {
     const int k = 4 * kk + lg;
-    double av[2];
+    double av[RT];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) av[b] = sx[(32 * wave + 16 * b + l16) * CP + k];
+    for (int b = 0; b < RT; ++b) av[b] = sx[(16 * RT * wave + 16 * b + l16) * CP + k];
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc) {
       const double bv = sm[k * CP + 16 * tc + l16];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[b][tc] = mfma_f64(av[b], bv, acc[b][tc]);
+      for (int b = 0; b < RT; ++b) acc[b][tc] = mfma_f64(av[b], bv, acc[b][tc]);
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < RT; ++b)
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int rr = 32 * wave + 16 * b + acc_row<double>(lg, e);
+        const int rr = 16 * RT * wave + 16 * b + acc_row<double>(lg, e);
         const int c = 16 * tc + l16;
         const double v = (r0 + rr < rows) ? acc[b][tc][e] : 0.0;
         sx[rr * CP + c] = v;
@@ -631,32 +632,32 @@ __global__ __launch_bounds__(CT) void k_cq_y(int rows, T* __restrict__ x, long l
     }
   }
   __syncthreads();
-  v4d acc[2][4];
+  v4d acc[RT][4];
 #pragma unroll
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < RT; ++b)
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc) acc[b][tc] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int kk = 0; kk < CB / 4; ++kk) {
     const int k = 4 * kk + lg;
-    double av[2];
+    double av[RT];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) av[b] = sx[(32 * wave + 16 * b + l16) * CP + k];
+    for (int b = 0; b < RT; ++b) av[b] = sx[(16 * RT * wave + 16 * b + l16) * CP + k];
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc) {
       const double bv = sm[k * CP + 16 * tc + l16];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[b][tc] = mfma_f64(av[b], bv, acc[b][tc]);
+      for (int b = 0; b < RT; ++b) acc[b][tc] = mfma_f64(av[b], bv, acc[b][tc]);
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < RT; ++b)
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int rr = 32 * wave + 16 * b + acc_row<double>(lg, e);
+        const int rr = 16 * RT * wave + 16 * b + acc_row<double>(lg, e);
         sx[rr * CP + 16 * tc + l16] = acc[b][tc][e];
       }
   __syncthreads();

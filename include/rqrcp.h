@@ -83,8 +83,8 @@ typedef struct rqrcp_ctx *rqrcp_handle;
                                 factored with those pivots; b <= 64, b + p <= 80 */
 
 typedef struct {
-  int b;           /* block size, 1 <= b <= 128 (Alg. 2 "block size b") */
-  int p;           /* oversampling, p >= 0, b + p <= 160 (Alg. 2 "oversampling size p") */
+  int b;           /* block size, 1 <= b <= 128 (the block size of Alg. 2) */
+  int p;           /* oversampling, p >= 0, b + p <= 160 (the oversampling of Alg. 2) */
   uint64_t seed;   /* Philox key word 0 of Omega (key word 1 = stream 0) */
   int a_type;      /* storage of A: RQRCP_F64, or RQRCP_F32 (then the trailing update
                       runs in FP32 and R, V are stored in FP32) */
@@ -120,7 +120,7 @@ int rqrcp_limits(int l, int *max_b, int *max_l, int *max_n);
 int rqrcp_gaussian(rqrcp_handle h, int rows, int cols, uint64_t seed, uint64_t stream,
                    double *out, int ld);
 
-/* Sketch B = Omega A (Alg. 2, "Compute B = Omega A"); A is m x n (lda) of
+/* Sketch B = Omega A (the sketching step of Alg. 2); A is m x n (lda) of
  * a_type (RQRCP_F64 or RQRCP_F32), B is l x n FP64 (ldb).  sketch_type is the
  * product's arithmetic (RQRCP_F64, RQRCP_BF16 or RQRCP_F8E4M3; see
  * rqrcp_params).  Omega: l x m FP64 (ldo) supplied by the caller, or NULL to

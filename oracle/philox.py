@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 The paper only asks for an i.i.d. N(0, 1) matrix Omega of size (b+p) x m
-(Alg. 2, "Generate i.i.d Gaussian matrix"; Alg. 3 draws a second one of size
+(the Gaussian sketching matrix of Alg. 2; Alg. 3 draws a second one of size
 d x (l+1)).  To let the oracle and the GPU library draw the *same* Omega from
 a seed without sharing any code, both implement one published generator:
 

@@ -19,7 +19,7 @@ Follows the paper step by step:
 
 Readings of points the paper leaves open (each one is listed in the design doc):
 
-* Householder convention (Alg. 1 "form Householder reflection"): LAPACK dlarfg,
+* Householder convention (the reflector step of Alg. 1): LAPACK dlarfg,
   beta = -sign(alpha) ||(alpha, x)||, sign(0) = +, tau = (beta - alpha)/beta,
   v = x/(alpha - beta); tau = 0 and no sign flip when x = 0.
 * Swaps are LAPACK-style sequential transpositions of whole columns (all rows of
@@ -51,7 +51,7 @@ from .philox import gauss
 
 
 # ---------------------------------------------------------------------------
-# Householder reflections (Alg. 1, "form Householder reflection")
+# Householder reflections (the reflector step of Alg. 1)
 # ---------------------------------------------------------------------------
 
 def householder(alpha: float, x: np.ndarray):

@@ -497,8 +497,8 @@ def main():
                          "(FP64), whose HBM counters calibrate the trailing update's")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
-                                   "sharding is a design (see DESIGN.md), not a measured path",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; sharding over "
+                                   "several GPUs is designed but not built or measured",
                           "n_gpus": args.gpus}))
         return 2
 

@@ -17,7 +17,7 @@ Follows the paper step by step:
 * Update formula (2) of Section III-B (B2 - Omega Q1 R12), for the equivalence
   check stated there (both formulas give the same permutations).
 
-Readings of points the paper leaves open (each one is listed in the design doc):
+Readings of points the paper leaves open:
 
 * Householder convention (the reflector step of Alg. 1): LAPACK dlarfg,
   beta = -sign(alpha) ||(alpha, x)||, sign(0) = +, tau = (beta - alpha)/beta,

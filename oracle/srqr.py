@@ -12,7 +12,7 @@ with the largest probed column norm to position l (round robin), restores the
 triangular form with Givens rotations, repivots the trailing candidates and
 repeats the QR step.
 
-Readings of points the paper leaves open (listed in the design doc):
+Readings of points the paper leaves open:
 
 * "Round Robin rotation": a cyclic shift; column i moves to position l and
   columns i+1..l move one position to the left.  The rows i..l of R are then

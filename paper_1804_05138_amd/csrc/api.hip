@@ -415,8 +415,9 @@ int factor_impl(rqrcp_ctx* h, int m, int n, int k, const rqrcp_params* prm, cons
   auto stacked_corr = [&](int c, int wd, T* wslot) -> int {
     const int cb = c + wd, nc = n - cb, kc = c - ob;
     PhaseTimer pt(h, RQRCP_PHASE_BUPDATE, 4.0 * wd * (double)kc * nc, 8.0 * (double)kc * nc);
-    const int tiles = ((2 * wd + 127) / 128) * ((nc + 127) / 128);
-    int sp = (256 + tiles - 1) / tiles;   // about one round of one workgroup per CU
+    // (64 x 64 output tiles for the 2 wd <= 128 rows of these products)
+    const int tiles = ((2 * wd + 63) / 64) * ((nc + 63) / 64);
+    int sp = (512 + tiles - 1) / tiles;   // about one round of two workgroups per CU
     sp = std::min(sp, std::max(1, kc / 32));
     sp = (int)std::min<long long>(sp, (long long)(gpart_elems / ((size_t)2 * wd * nc)));
     sp = std::max(sp, 1);

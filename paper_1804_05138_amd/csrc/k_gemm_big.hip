@@ -405,7 +405,7 @@ int big_tiles(bool ta, int M, int N) {
   int bm = 128, bn = 128;
   if (ta && M <= 64) { bm = 64; bn = 256; }
   else if (!ta && M <= 64) { bm = 64; bn = 128; }
-  else if (!ta && N <= 64) { bm = 64; bn = 64; }
+  else if (!ta && (N <= 64 || M <= 128)) { bm = 64; bn = 64; }
   return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
 }
 
@@ -430,7 +430,8 @@ void big_launch(hipStream_t s, bool ta, int M, int N, int K, T alpha, const T* A
     if (M <= 64)
       launch_big<T, false, 1, 2, kBK, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
                                          kchunk, nsplit, part);
-    else if (N <= 64)   // 64 x 64 tiles as four waves of 32 x 32 (tall products: more tiles)
+    else if (N <= 64 || M <= 128)   // 64 x 64 tiles as four waves of 32 x 32 (narrow or
+                                    // short products: more tiles)
       launch_big<T, false, 2, 2, kBK, 2, 2, 2>(s, vec, M, N, K, alpha, A, lda, B, ldb, beta, C,
                                                ldc, kchunk, nsplit, part);
     else  // 128 x 128 tiles as eight waves of 64 x 32 (two workgroups per CU; 1.4%
